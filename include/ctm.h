@@ -1,0 +1,152 @@
+/*
+ * ctm.h -- C interface of libctm: C3v-symmetric QR-based CTMRG for honeycomb
+ * iPEPS on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Q. Yang and P. Corboz, "Efficient iPEPS Simulation on the Honeycomb
+ * Lattice via QR-based CTMRG", arXiv:2509.05090.
+ *
+ * Conventions shared by all calls
+ *  - Site tensor A[s][u][v][w]: d x D x D x D, row-major FP64, real, projected
+ *    onto the C3v-symmetric subspace of the trivial irrep (Appendix A:
+ *    invariant under all permutations of the three virtual legs u, v, w).
+ *  - Double layer a[I][J][K], I = u*D + u' (Sec. II.A, Fig. 1b).
+ *  - Corner C[gamma][delta] (chi_c x chi_c), edge T[alpha][i][gamma]
+ *    (chi_c x D^2 x chi_c; outer leg, end leg towards the apex, inner leg),
+ *    projector P[(alpha,k)][mu] (chi_c D^2 x chi), all row-major FP64.
+ *  - A local pair b[i][j][k][l] = sum_m a[i][j][m] a[m][k][l] is the four-leg
+ *    tensor of the local mapping (Fig. 1c); one step enlarges the corner by a
+ *    pair and two edges and renormalizes corner and edge with an isometry
+ *    (Fig. 3a,b).
+ *  - Device pointers are HIP device memory owned by the caller; `stream` is a
+ *    hipStream_t (NULL = the default stream) on which all device work of a
+ *    context is enqueued.  A call synchronizes the stream only when it returns
+ *    values in host memory.
+ *  - Every call returns CTM_OK (0) or a negative status; ctm_last_error()
+ *    gives the reason.  After CTM_EDEVICE the context is unusable and may only
+ *    be freed.  A context is not thread-safe; separate contexts are
+ *    independent.
+ */
+#ifndef CTM_H
+#define CTM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  CTM_OK = 0,
+  CTM_EINVAL = -1,     /* bad size, enum value or null pointer */
+  CTM_ENOTSYM = -2,    /* ||A - sym(A)||_F > 1e-12 ||A||_F */
+  CTM_ENOMEM = -3,     /* device allocation failed */
+  CTM_EDEVICE = -4,    /* HIP runtime error; context poisoned */
+  CTM_ENOTCONV = -5,   /* tolerance not reached within max_steps (state stays valid) */
+  CTM_ENONFINITE = -6, /* NaN/Inf or zero norm in C or T */
+  CTM_ESTATE = -7      /* call not valid in the current state */
+};
+
+/* Projector of the CTMRG step (Sec. II.B).
+ * CTM_PROJ_QR:  thin QR of the chi_c D^2 x chi reduced corner M = Ct P_prev
+ *               (Fig. 3d); Q is the new isometry.  One sweep of orthogonal
+ *               iteration per step: at a fixed point Q spans a dominant
+ *               eigenspace of the enlarged corner Ct.
+ * CTM_PROJ_EVD: eigenvectors of Ct of the chi largest |eigenvalues|
+ *               (Fig. 3c).  Reserved; not implemented by this library yet. */
+typedef enum { CTM_PROJ_QR = 0, CTM_PROJ_EVD = 1 } ctm_proj;
+
+/* Arithmetic of the contractions.  The QR, the sign gauge, the
+ * normalization of C and T and the energy are FP64 in every mode; the master
+ * copies of C, T and P are FP64.  FP32 and BF16 run the contractions on FP32
+ * and BF16 matrix cores with FP32 accumulation. */
+typedef enum { CTM_PREC_FP64 = 0, CTM_PREC_FP32 = 1, CTM_PREC_BF16 = 2 } ctm_prec;
+
+typedef struct {
+  int d;        /* physical dimension, >= 1 */
+  int D;        /* virtual bond dimension, >= 1 */
+  int chi;      /* environment bond dimension, >= 1 */
+  int proj;     /* ctm_proj */
+  int prec;     /* ctm_prec */
+} ctm_config;
+
+typedef struct ctm_ctx ctm_ctx;
+
+/* Project a raw tensor onto the C3v-symmetric subspace (Appendix A, trivial
+ * irrep: mean over the 6 permutations of the virtual legs) and normalize it
+ * to unit Frobenius norm.  raw_dev and A_dev: d*D^3 FP64 device arrays (may
+ * alias).  Errors: CTM_EINVAL, CTM_ENONFINITE (zero projection). */
+int ctm_symmetrize(const double *raw_dev, double *A_dev, int d, int D, void *stream);
+
+/* Create a context.  Copies A (d*D^3, must be C3v-symmetric, else
+ * CTM_ENOTSYM) and G (chi*D^2 x chi seeded N(0,1) start matrix: the first
+ * projector of an n-row reduced corner is the Gram-Schmidt basis of G's
+ * first n rows).  Builds the double layer and the small start environment
+ * C = [[1]], T[0][(u,u')][0] = delta_{u u'} (chi_c = 1), and allocates all
+ * device memory the run needs.  Errors: CTM_EINVAL, CTM_ENOTSYM, CTM_ENOMEM,
+ * CTM_EDEVICE. */
+int ctm_init(ctm_ctx **out, const ctm_config *cfg, const double *A_dev, const double *G_dev,
+             void *stream);
+
+/* Run n_steps >= 0 CTMRG steps (Fig. 3a,b; Sec. II.B): enlarged corner
+ * Ct[(alpha,k),(beta,l)] = sum T[alpha,i,gamma] C[gamma,delta] T[beta,j,delta]
+ * a[i,j,m] a[m,k,l]; projector Q (identity while chi_c D^2 <= chi);
+ * C' = Q^T Ct Q symmetrized and T' = Q^T (T b) Q, both Frobenius-normalized.
+ * Column signs of Q follow the previous projector.  Nothing is synchronized
+ * unless delta_host is non-null; then it receives the change of the
+ * normalized corner spectrum across the last step (INFINITY if undefined).
+ * Errors: CTM_EINVAL, CTM_ENONFINITE, CTM_EDEVICE. */
+int ctm_step(ctm_ctx *c, int n_steps, double *delta_host);
+
+/* Iterate until the corner-spectrum change is below tol, checking every
+ * n_check >= 1 steps, or until max_steps steps were run.  steps_host and
+ * delta_host (nullable) receive the steps taken and the last change.
+ * Returns CTM_ENOTCONV if tol was not reached (the state stays usable). */
+int ctm_converge(ctm_ctx *c, double tol, int max_steps, int n_check, int *steps_host,
+                 double *delta_host);
+
+/* Bond energy from the current environment (Sec. II.C, Fig. 4b): the
+ * enlarged corner with the physical legs of its apex pair open, traced
+ * against the rest of the six-corner ring Env = Q (Q^T Ct Q)^5 Q^T, where Q
+ * is the projector the run's rule gives for the current state (the state is
+ * not changed).  h_host: d^2 x d^2 row-major operator on (outer site, inner
+ * site) of the pair.  e_host receives Tr(rho h)/Tr(rho); rho_host (nullable,
+ * d^2 x d^2) the unit-trace bond density matrix rho[(s,t),(s',t')].  FP64.
+ * Errors: CTM_EINVAL, CTM_ENONFINITE, CTM_EDEVICE. */
+int ctm_energy(ctm_ctx *c, const double *h_host, double *e_host, double *rho_host);
+
+/* Normalized corner spectrum of the current state: |eigenvalues| of C in
+ * decreasing order divided by the largest.  s_host must hold chi values;
+ * n_host receives chi_c.  Synchronizes.  Errors: CTM_EINVAL, CTM_EDEVICE. */
+int ctm_spectrum(ctm_ctx *c, double *s_host, int *n_host);
+
+/* Current sizes: chi_c, steps run so far, and the rows of the stored
+ * projector (0 before the first truncation).  Any pointer may be null. */
+int ctm_query(const ctm_ctx *c, int *chi_c, int *steps, int *p_rows);
+
+/* Copy the environment into caller device buffers (C: chi_c^2, T:
+ * chi_c*D^2*chi_c, P: p_rows*chi, each nullable).  Enqueued on the stream. */
+int ctm_get_env(ctm_ctx *c, double *C_dev, double *T_dev, double *P_dev);
+
+/* Replace the environment by caller device data of corner dimension chi_c
+ * (1 <= chi_c <= chi) and a projector of p_rows rows (0 = none; else
+ * p_rows = chi_c*D^2 of the state that produced it, P_dev non-null).
+ * Enqueued on the stream.  Errors: CTM_EINVAL. */
+int ctm_set_env(ctm_ctx *c, int chi_c, const double *C_dev, const double *T_dev, int p_rows,
+                const double *P_dev);
+
+/* Switch the contraction arithmetic of an existing context (for a precision
+ * ladder: low precision far from convergence, FP64 near it). */
+int ctm_set_precision(ctm_ctx *c, int prec);
+
+/* Free a context and all its device memory (null is ignored). */
+void ctm_free(ctm_ctx *c);
+
+/* Text of the last error of c, or of the last failed ctm_init/
+ * ctm_symmetrize when c is null.  Valid until the next call on c. */
+const char *ctm_last_error(const ctm_ctx *c);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CTM_H */

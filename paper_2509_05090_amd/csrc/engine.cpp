@@ -1,0 +1,654 @@
+// CTMRG engine and C interface (see include/ctm.h).
+//
+// One step of the C3v-symmetric CTMRG on the honeycomb lattice (Sec. II.B,
+// Fig. 3), as a schedule of MFMA matrix products.  Indices: chi_c = current
+// corner dimension, D2 = D^2, n = chi_c * D2.
+//
+//   1. TCp[beta][gamma][j]  = sum_delta C[gamma][delta] T[beta][j][delta]
+//        chi_c products of (chi_c x D2), k = chi_c: corner onto the column edge
+//   2. V[(alpha,m)][(gamma,j)] = sum_i T[alpha][i][gamma] a[m][i][j]
+//        chi_c*D2 products of (chi_c x D2), k = D2: outer site of the pair on
+//        the row edge (the double layer is symmetric in its legs)
+//   3. W[(alpha,m)][beta]   = V . TCp^T               (n x chi_c, k = n)
+//   4. Ct[(alpha,k)][(beta,l)] = sum_m W[(alpha,m)][beta] a[m][k][l]
+//        chi_c*D2 products (chi_c x D2), k = D2: inner site; Ct is the n x n
+//        enlarged corner, symmetric
+//   5. projector Q (n x chi): identity while n <= chi; else the thin QR of
+//        the reduced corner M = Ct . P_prev (n x chi, k = n), FP64 blocked
+//        Householder, column signs aligned with P_prev, P_prev <- Q
+//   6. Gm = Ct . Q                                    (n x chi, k = n)
+//   7. C' = Q^T . Gm, then (C' + C'^T)/2 / ||.||_F     (chi x chi, k = n)
+//   8. V2 = V . Q                                     (n x chi, k = n)
+//   9. V3[alpha][(k,l)][nu] = sum_m a[k][l][m] V2[(alpha,m)][nu]
+//        chi_c products of (D2*D2 x chi), k = D2
+//  10. T' = Q^T . V3 (V3 read as n x (D2 chi)), then / ||.||_F
+//
+// Steps 1-4 and 6-10 run in the context's arithmetic (FP64, or FP32/BF16
+// matrix cores with FP32 accumulation); the QR, sign gauge and norms are
+// FP64, as are the master copies of C, T and P_prev.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ctm.h"
+#include "gemm.hpp"
+#include "kernels.hpp"
+#include "qr.hpp"
+#include "spectrum.hpp"
+
+using namespace ctm;
+
+namespace {
+
+thread_local std::string g_error;
+
+struct OutOfMemory : std::runtime_error {
+  explicit OutOfMemory(const std::string& s) : std::runtime_error(s) {}
+};
+
+}  // namespace
+
+namespace ctm {
+void set_global_error(const std::string& s) { g_error = s; }
+}  // namespace ctm
+
+struct ctm_ctx {
+  ctm_config cfg{};
+  hipStream_t stream = nullptr;
+  std::string err;
+  bool poisoned = false;
+  int d = 0, D = 0, D2 = 0, chi = 0;
+  int64_t nmax = 0;
+  int chi_c = 1, steps = 0, p_rows = 0;
+  DType prec = DType::F64;
+
+  std::vector<void*> allocations;
+
+  // FP64 state and inputs
+  double *A = nullptr, *a = nullptr, *aO = nullptr, *aOr = nullptr, *G = nullptr;
+  double *C = nullptr, *T = nullptr, *Cn = nullptr, *Tn = nullptr, *P = nullptr;
+  // FP64 work
+  double *M = nullptr, *Q = nullptr, *Cp = nullptr, *Tp = nullptr;
+  double *sgn = nullptr, *part = nullptr, *sumsq = nullptr, *dev_small = nullptr;
+  int* flag = nullptr;
+  // Intermediates; allocated with 8-byte elements so that they hold any precision.
+  void *aE = nullptr, *CE = nullptr, *TE = nullptr, *PE = nullptr, *QE = nullptr;
+  void *TCp = nullptr, *V = nullptr, *W = nullptr, *Ct = nullptr, *Gm = nullptr, *V2 = nullptr;
+  // energy
+  double *XO = nullptr, *EO = nullptr, *Cr2 = nullptr, *Cr4 = nullptr, *Cr5 = nullptr;
+  double *rho_raw = nullptr, *h_dev = nullptr, *e_out = nullptr;
+  QrWork qr;
+  Scratch ws;
+
+  // spectrum cache (host)
+  std::vector<double> spec;
+  int spec_step = -1;
+
+  void* alloc(size_t bytes) {
+    void* p = nullptr;
+    if (bytes == 0) bytes = 8;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      throw OutOfMemory("hipMalloc(" + std::to_string(bytes) + ") failed: " + hipGetErrorString(e));
+    }
+    allocations.push_back(p);
+    return p;
+  }
+  double* allocd(int64_t n) { return (double*)alloc((size_t)n * sizeof(double)); }
+
+  ~ctm_ctx() {
+    if (stream) (void)hipStreamSynchronize(stream);
+    for (void* p : allocations) (void)hipFree(p);
+  }
+};
+
+namespace {
+
+template <typename F>
+int guarded(ctm_ctx* c, F&& f) {
+  if (!c) {
+    g_error = "null context";
+    return CTM_EINVAL;
+  }
+  if (c->poisoned) {
+    c->err = "context unusable after a device error: " + c->err;
+    return CTM_EDEVICE;
+  }
+  try {
+    return f();
+  } catch (const DeviceError& e) {
+    c->poisoned = true;
+    c->err = e.what();
+    return CTM_EDEVICE;
+  } catch (const OutOfMemory& e) {
+    c->err = e.what();
+    return CTM_ENOMEM;
+  } catch (const std::bad_alloc&) {
+    c->err = "host allocation failed";
+    return CTM_ENOMEM;
+  } catch (const std::exception& e) {
+    c->err = e.what();
+    return CTM_EINVAL;
+  }
+}
+
+DType to_dtype(int prec) {
+  return prec == CTM_PREC_FP32 ? DType::F32 : (prec == CTM_PREC_BF16 ? DType::BF16 : DType::F64);
+}
+
+// Working-precision views of FP64 data: the FP64 buffer itself in FP64 mode,
+// else a converted copy in `scratch`.
+const void* as_prec(ctm_ctx* c, const double* src, void* scratch, int64_t n) {
+  if (c->prec == DType::F64) return src;
+  launch_cast(c->stream, src, scratch, c->prec, n);
+  return scratch;
+}
+
+bool read_flag(ctm_ctx* c) {
+  int f = 0;
+  CTM_HIP(hipMemcpyAsync(&f, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  CTM_HIP(hipStreamSynchronize(c->stream));
+  return f != 0;
+}
+
+std::vector<double> current_spectrum(ctm_ctx* c) {
+  std::vector<double> h((size_t)c->chi_c * c->chi_c);
+  CTM_HIP(hipMemcpyAsync(h.data(), c->C, h.size() * sizeof(double), hipMemcpyDeviceToHost,
+                         c->stream));
+  CTM_HIP(hipStreamSynchronize(c->stream));
+  return normalized_spectrum(h, c->chi_c);
+}
+
+// P_prev <- Gram-Schmidt basis of the first n rows of G (unique: diag(R) > 0),
+// written to `dst` (n x chi).
+void start_projector(ctm_ctx* c, int n, double* dst) {
+  hipStream_t s = c->stream;
+  const int chi = c->chi;
+  CTM_HIP(hipMemcpyAsync(c->M, c->G, (size_t)n * chi * sizeof(double), hipMemcpyDeviceToDevice, s));
+  householder_qr(s, c->M, chi, n, chi, c->qr);
+  householder_form_q(s, c->qr, n, chi, dst, chi);
+  launch_diag_signs(s, c->M, chi, chi, c->sgn);
+  launch_apply_signs(s, dst, n, chi, c->sgn, nullptr);
+}
+
+// Enlarged corner of the current state into c->Ct (steps 1-4), arithmetic e.
+// Leaves TCp, V, W valid.
+void enlarged_corner(ctm_ctx* c, DType e) {
+  hipStream_t s = c->stream;
+  const int x = c->chi_c, D2 = c->D2;
+  const int64_t n = (int64_t)x * D2;
+  const void *CE, *TE, *aE;
+  if (e == DType::F64) {
+    CE = c->C;
+    TE = c->T;
+    aE = c->a;
+  } else {
+    launch_cast(s, c->C, c->CE, e, (int64_t)x * x);
+    launch_cast(s, c->T, c->TE, e, (int64_t)x * D2 * x);
+    CE = c->CE;
+    TE = c->TE;
+    aE = c->aE;
+    launch_cast(s, c->a, c->aE, e, (int64_t)D2 * D2 * D2);
+  }
+  // 1. TCp[beta][gamma][j]
+  gemm(s, e, x, D2, x, Operand{CE, x, false}, Operand{TE, x, true, (int64_t)D2 * x},
+       Output{c->TCp, D2, e, (int64_t)x * D2}, x, 1, 1.0, 0.0, c->ws);
+  // 2. V[(alpha,m)][(gamma,j)]
+  gemm(s, e, x, D2, D2, Operand{TE, x, true, (int64_t)D2 * x, 0},
+       Operand{aE, D2, false, 0, (int64_t)D2 * D2}, Output{c->V, D2, e, D2 * n, n}, x, D2, 1.0,
+       0.0, c->ws);
+  // 3. W = V TCp^T
+  gemm(s, e, (int)n, x, (int)n, Operand{c->V, n, false}, Operand{c->TCp, n, true},
+       Output{c->W, x, e}, 1, 1, 1.0, 0.0, c->ws);
+  // 4. Ct[(alpha,k)][(beta,l)]
+  gemm(s, e, x, D2, D2, Operand{c->W, x, true, (int64_t)D2 * x, 0},
+       Operand{aE, (int64_t)D2 * D2, false, 0, D2}, Output{c->Ct, D2, e, D2 * n, n}, x, D2, 1.0,
+       0.0, c->ws);
+}
+
+// Projector of the QR rule for the current Ct into c->Q (FP64, n x chi,
+// ld chi), sign-aligned with the stored P_prev (or the start projector when
+// P_prev does not match n).  If update, P_prev <- Q.
+void qr_projector(ctm_ctx* c, DType e, bool update) {
+  hipStream_t s = c->stream;
+  const int chi = c->chi;
+  const int n = c->chi_c * c->D2;
+  double* Pref = c->P;
+  if (c->p_rows != n) {
+    if (update) {
+      start_projector(c, n, c->P);
+      c->p_rows = n;
+    } else {
+      Pref = (double*)c->PE;  // 8-byte scratch of n x chi
+      start_projector(c, n, Pref);
+    }
+  }
+  const void* PE = as_prec(c, Pref, e == DType::F64 ? nullptr : c->PE, (int64_t)n * chi);
+  if (e != DType::F64 && Pref == (double*)c->PE)
+    throw std::logic_error("projector scratch clash");
+  // 5. M = Ct P_prev (FP64 result)
+  gemm(s, e, n, chi, n, Operand{c->Ct, n, false}, Operand{PE, chi, false},
+       Output{c->M, chi, DType::F64}, 1, 1, 1.0, 0.0, c->ws);
+  householder_qr(s, c->M, chi, n, chi, c->qr);
+  householder_form_q(s, c->qr, n, chi, c->Q, chi);
+  launch_overlap_signs(s, Pref, c->Q, n, chi, c->part, c->sgn);
+  launch_apply_signs(s, c->Q, n, chi, c->sgn, update ? c->P : nullptr);
+}
+
+void step_once(ctm_ctx* c) {
+  hipStream_t s = c->stream;
+  const DType e = c->prec;
+  const int x = c->chi_c, D2 = c->D2, chi = c->chi;
+  const int64_t n = (int64_t)x * D2;
+  enlarged_corner(c, e);
+  int xn;
+  if (n <= chi) {
+    xn = (int)n;
+    launch_eye(s, c->Q, DType::F64, (int)n, (int)n, n);
+  } else {
+    xn = chi;
+    qr_projector(c, e, true);
+  }
+  const void* QE = as_prec(c, c->Q, c->QE, n * xn);
+  // 6. Gm = Ct Q
+  gemm(s, e, (int)n, xn, (int)n, Operand{c->Ct, n, false}, Operand{QE, xn, false},
+       Output{c->Gm, xn, e}, 1, 1, 1.0, 0.0, c->ws);
+  // 7. C' = Q^T Gm, symmetrized and normalized
+  gemm(s, e, xn, xn, (int)n, Operand{QE, xn, true}, Operand{c->Gm, xn, false},
+       Output{c->Cp, xn, DType::F64}, 1, 1, 1.0, 0.0, c->ws);
+  launch_corner_finalize(s, c->Cp, c->Cn, xn, c->flag);
+  // 8. V2 = V Q
+  gemm(s, e, (int)n, xn, (int)n, Operand{c->V, n, false}, Operand{QE, xn, false},
+       Output{c->V2, xn, e}, 1, 1, 1.0, 0.0, c->ws);
+  // 9. V3[alpha][(k,l)][nu] into the Ct buffer (Ct is no longer needed)
+  const void* aE = e == DType::F64 ? (const void*)c->a : c->aE;
+  void* V3 = c->Ct;
+  gemm(s, e, D2 * D2, xn, D2, Operand{aE, D2, false, 0}, Operand{c->V2, xn, false, (int64_t)D2 * xn},
+       Output{V3, xn, e, (int64_t)D2 * D2 * xn}, x, 1, 1.0, 0.0, c->ws);
+  // 10. T' = Q^T V3, normalized
+  const int64_t tn = (int64_t)xn * D2 * xn;
+  gemm(s, e, xn, D2 * xn, (int)n, Operand{QE, xn, true}, Operand{V3, (int64_t)D2 * xn, false},
+       Output{c->Tp, (int64_t)D2 * xn, DType::F64}, 1, 1, 1.0, 0.0, c->ws, 0, c->sumsq);
+  launch_scale_by_norm(s, c->Tp, c->Tn, tn, c->sumsq, sumsq_blocks(xn, D2 * xn), c->flag);
+  std::swap(c->C, c->Cn);
+  std::swap(c->T, c->Tn);
+  c->chi_c = xn;
+  c->steps += 1;
+}
+
+int do_steps(ctm_ctx* c, int n_steps, double* delta) {
+  if (n_steps < 0) throw std::invalid_argument("n_steps < 0");
+  for (int i = 0; i < n_steps; ++i) {
+    if (delta && i == n_steps - 1 && c->spec_step != c->steps) {
+      c->spec = current_spectrum(c);
+      c->spec_step = c->steps;
+    }
+    step_once(c);
+  }
+  if (delta) {
+    if (n_steps == 0 || c->spec_step != c->steps - 1) {
+      *delta = std::numeric_limits<double>::infinity();
+      if (n_steps > 0) {
+        c->spec = current_spectrum(c);
+        c->spec_step = c->steps;
+      }
+    } else {
+      std::vector<double> sn = current_spectrum(c);
+      *delta = spectrum_change(sn, c->spec);
+      c->spec = std::move(sn);
+      c->spec_step = c->steps;
+    }
+    if (read_flag(c)) {
+      c->err = "non-finite or zero norm in C or T";
+      return CTM_ENONFINITE;
+    }
+  }
+  return CTM_OK;
+}
+
+void ensure_energy_buffers(ctm_ctx* c) {
+  if (c->XO) return;
+  const int64_t x2 = (int64_t)c->chi * c->chi;
+  const int64_t dd = (int64_t)c->d * c->d;
+  c->XO = c->allocd(x2 * c->D2 * dd);
+  c->EO = c->allocd(x2 * c->D2 * dd);
+  c->aO = c->allocd((int64_t)c->D2 * c->D2 * c->D2 * dd);
+  c->aOr = c->allocd((int64_t)c->D2 * c->D2 * c->D2 * dd);
+  c->Cr2 = c->allocd(x2);
+  c->Cr4 = c->allocd(x2);
+  c->Cr5 = c->allocd(x2);
+  c->rho_raw = c->allocd(dd * dd);
+  c->h_dev = c->allocd(dd * dd);
+  c->e_out = c->allocd(1 + dd * dd);
+  launch_double_layer_open(c->stream, c->A, c->d, c->D, 0, c->aO);
+  launch_double_layer_open(c->stream, c->A, c->d, c->D, 1, c->aOr);
+}
+
+// Bond density matrix of the apex pair on the six-corner ring (FP64).
+int do_energy(ctm_ctx* c, const double* h_host, double* e_host, double* rho_host) {
+  hipStream_t s = c->stream;
+  ensure_energy_buffers(c);
+  const DType f = DType::F64;
+  const int x = c->chi_c, D2 = c->D2, chi = c->chi, d = c->d;
+  const int dd = d * d;
+  const int64_t n = (int64_t)x * D2;
+  CTM_HIP(hipMemcpyAsync(c->h_dev, h_host, (size_t)dd * dd * sizeof(double), hipMemcpyHostToDevice, s));
+  enlarged_corner(c, f);
+  int xm;
+  if (n <= chi) {
+    xm = (int)n;
+    launch_eye(s, c->Q, f, (int)n, (int)n, n);
+  } else {
+    xm = chi;
+    qr_projector(c, f, false);
+  }
+  double* Ct = (double*)c->Ct;
+  double* Gm = (double*)c->Gm;
+  // Cr = Q^T Ct Q, scaled; its fifth power
+  gemm(s, f, (int)n, xm, (int)n, Operand{Ct, n, false}, Operand{c->Q, xm, false}, Output{Gm, xm, f},
+       1, 1, 1.0, 0.0, c->ws);
+  gemm(s, f, xm, xm, (int)n, Operand{c->Q, xm, true}, Operand{Gm, xm, false}, Output{c->Cp, xm, f},
+       1, 1, 1.0, 0.0, c->ws);
+  launch_scale_by_maxabs(s, c->Cp, xm);
+  gemm(s, f, xm, xm, xm, Operand{c->Cp, xm, false}, Operand{c->Cp, xm, false},
+       Output{c->Cr2, xm, f}, 1, 1, 1.0, 0.0, c->ws);
+  gemm(s, f, xm, xm, xm, Operand{c->Cr2, xm, false}, Operand{c->Cr2, xm, false},
+       Output{c->Cr4, xm, f}, 1, 1, 1.0, 0.0, c->ws);
+  gemm(s, f, xm, xm, xm, Operand{c->Cr4, xm, false}, Operand{c->Cp, xm, false},
+       Output{c->Cr5, xm, f}, 1, 1, 1.0, 0.0, c->ws);
+  // QC5 = Q Cr^5 (into W)
+  double* QC5 = (double*)c->W;
+  gemm(s, f, (int)n, xm, xm, Operand{c->Q, xm, false}, Operand{c->Cr5, xm, false},
+       Output{QC5, xm, f}, 1, 1, 1.0, 0.0, c->ws);
+  // EnvP[alpha][beta][K][L] = Env[(beta,L),(alpha,K)] = sum_nu Q[(alpha,K)][nu] QC5[(beta,L)][nu]
+  double* EnvP = (double*)c->V;
+  gemm(s, f, D2, D2, xm, Operand{c->Q, xm, false, (int64_t)D2 * xm, 0},
+       Operand{QC5, xm, true, 0, (int64_t)D2 * xm},
+       Output{EnvP, D2, f, (int64_t)x * D2 * D2, (int64_t)D2 * D2}, x, x, 1.0, 0.0, c->ws);
+  // TCTp[alpha][beta][I][J] = sum_gamma T[alpha][I][gamma] TCp[beta][gamma][J]  (into Ct)
+  double* TCTp = Ct;
+  gemm(s, f, D2, D2, x, Operand{c->T, x, false, (int64_t)D2 * x, 0},
+       Operand{c->TCp, D2, false, 0, (int64_t)x * D2},
+       Output{TCTp, D2, f, (int64_t)x * D2 * D2, (int64_t)D2 * D2}, x, x, 1.0, 0.0, c->ws);
+  // outer site open: XO[(alpha,beta)][(M,s,s')]; inner site open with the ring: EO
+  const int64_t x2 = (int64_t)x * x;
+  gemm(s, f, (int)x2, D2 * dd, D2 * D2, Operand{TCTp, (int64_t)D2 * D2, false},
+       Operand{c->aO, (int64_t)D2 * dd, false}, Output{c->XO, (int64_t)D2 * dd, f}, 1, 1, 1.0, 0.0,
+       c->ws);
+  gemm(s, f, (int)x2, D2 * dd, D2 * D2, Operand{EnvP, (int64_t)D2 * D2, false},
+       Operand{c->aOr, (int64_t)D2 * dd, false}, Output{c->EO, (int64_t)D2 * dd, f}, 1, 1, 1.0,
+       0.0, c->ws);
+  // R[(s,s')][(t,t')] = sum_{(alpha,beta,M)} XO[..][(s,s')] EO[..][(t,t')]
+  gemm(s, f, dd, dd, (int)(x2 * D2), Operand{c->XO, dd, true}, Operand{c->EO, dd, false},
+       Output{c->rho_raw, dd, f}, 1, 1, 1.0, 0.0, c->ws);
+  launch_energy_finalize(s, c->rho_raw, c->h_dev, d, c->e_out, c->flag);
+  std::vector<double> out(1 + (size_t)dd * dd);
+  CTM_HIP(hipMemcpyAsync(out.data(), c->e_out, out.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  CTM_HIP(hipStreamSynchronize(s));
+  if (read_flag(c)) {
+    c->err = "non-finite or zero norm in C, T or the density matrix";
+    return CTM_ENONFINITE;
+  }
+  if (e_host) *e_host = out[0];
+  if (rho_host) std::memcpy(rho_host, out.data() + 1, (size_t)dd * dd * sizeof(double));
+  return CTM_OK;
+}
+
+bool valid_cfg(const ctm_config* cfg, std::string& why) {
+  if (!cfg) return why = "null config", false;
+  if (cfg->d < 1 || cfg->D < 1 || cfg->chi < 1) return why = "d, D and chi must be >= 1", false;
+  if ((int64_t)cfg->d * cfg->D * cfg->D * cfg->D > 16384) return why = "d*D^3 > 16384", false;
+  if ((int64_t)cfg->chi * cfg->D * cfg->D > (1 << 20)) return why = "chi*D^2 too large", false;
+  if (cfg->proj != CTM_PROJ_QR)
+    return why = "only the QR projector (CTM_PROJ_QR) is implemented", false;
+  if (cfg->prec < CTM_PREC_FP64 || cfg->prec > CTM_PREC_BF16) return why = "bad precision", false;
+  return true;
+}
+
+void allocate(ctm_ctx* c) {
+  const int64_t D2 = c->D2, chi = c->chi, nmax = c->nmax;
+  const int64_t dA = (int64_t)c->d * c->D * c->D * c->D;
+  c->A = c->allocd(dA);
+  c->a = c->allocd(D2 * D2 * D2);
+  c->G = c->allocd(nmax * chi);
+  c->C = c->allocd(chi * chi);
+  c->Cn = c->allocd(chi * chi);
+  c->T = c->allocd(chi * D2 * chi);
+  c->Tn = c->allocd(chi * D2 * chi);
+  c->P = c->allocd(nmax * chi);
+  c->M = c->allocd(nmax * chi);
+  c->Q = c->allocd(nmax * chi);
+  c->Cp = c->allocd(chi * chi);
+  c->Tp = c->allocd(chi * D2 * chi);
+  c->sgn = c->allocd(chi);
+  c->part = c->allocd((int64_t)overlap_blocks((int)nmax) * chi);
+  c->sumsq = c->allocd(1024);
+  c->dev_small = c->allocd(8);
+  c->flag = (int*)c->alloc(sizeof(int) * 4);
+  c->aE = c->allocd(D2 * D2 * D2);
+  c->CE = c->allocd(chi * chi);
+  c->TE = c->allocd(chi * D2 * chi);
+  c->PE = c->allocd(nmax * chi);
+  c->QE = c->allocd(nmax * chi);
+  c->TCp = c->allocd(chi * nmax);
+  c->V = c->allocd(nmax * nmax);
+  c->W = c->allocd(nmax * chi);
+  c->Ct = c->allocd(nmax * nmax);
+  c->Gm = c->allocd(nmax * chi);
+  c->V2 = c->allocd(nmax * chi);
+  c->qr.Y = c->allocd(nmax * chi);
+  c->qr.tau = c->allocd(chi);
+  c->qr.Tf = c->allocd(cdiv(chi, QR_NB) * QR_NB * QR_NB);
+  c->qr.W = c->allocd((int64_t)QR_NB * chi);
+  c->qr.W2 = c->allocd((int64_t)QR_NB * chi);
+  c->qr.ws.bytes = gemm_scratch_bytes(DType::F64, QR_NB, (int)chi);
+  c->qr.ws.p = c->alloc(c->qr.ws.bytes);
+  size_t wsb = std::max(gemm_scratch_bytes(DType::F64, (int)nmax, (int)chi),
+                        gemm_scratch_bytes(DType::F64, (int)chi, (int)chi));
+  c->ws.bytes = wsb;
+  c->ws.p = c->alloc(wsb);
+}
+
+}  // namespace
+
+extern "C" {
+
+int ctm_symmetrize(const double* raw_dev, double* A_dev, int d, int D, void* stream) {
+  if (!raw_dev || !A_dev || d < 1 || D < 1 || (int64_t)d * D * D * D > 16384) {
+    g_error = "ctm_symmetrize: bad arguments";
+    return CTM_EINVAL;
+  }
+  try {
+    hipStream_t s = (hipStream_t)stream;
+    double* tmp = nullptr;
+    CTM_HIP(hipMalloc(&tmp, sizeof(double)));
+    launch_symmetrize(s, raw_dev, A_dev, d, D, tmp);
+    double n2 = 0.0;
+    CTM_HIP(hipMemcpyAsync(&n2, tmp, sizeof(double), hipMemcpyDeviceToHost, s));
+    CTM_HIP(hipStreamSynchronize(s));
+    CTM_HIP(hipFree(tmp));
+    if (!(n2 > 0.0) || !std::isfinite(n2)) {
+      g_error = "ctm_symmetrize: the symmetric projection is zero or not finite";
+      return CTM_ENONFINITE;
+    }
+    return CTM_OK;
+  } catch (const std::exception& e) {
+    g_error = e.what();
+    return CTM_EDEVICE;
+  }
+}
+
+int ctm_init(ctm_ctx** out, const ctm_config* cfg, const double* A_dev, const double* G_dev,
+             void* stream) {
+  if (!out || !A_dev || !G_dev) {
+    g_error = "ctm_init: null pointer";
+    return CTM_EINVAL;
+  }
+  *out = nullptr;
+  std::string why;
+  if (!valid_cfg(cfg, why)) {
+    g_error = "ctm_init: " + why;
+    return CTM_EINVAL;
+  }
+  std::unique_ptr<ctm_ctx> c(new (std::nothrow) ctm_ctx());
+  if (!c) {
+    g_error = "ctm_init: host allocation failed";
+    return CTM_ENOMEM;
+  }
+  c->cfg = *cfg;
+  c->stream = (hipStream_t)stream;
+  c->d = cfg->d;
+  c->D = cfg->D;
+  c->D2 = cfg->D * cfg->D;
+  c->chi = cfg->chi;
+  c->nmax = (int64_t)cfg->chi * c->D2;
+  c->prec = to_dtype(cfg->prec);
+  int rc = guarded(c.get(), [&]() -> int {
+    allocate(c.get());
+    hipStream_t s = c->stream;
+    const int64_t dA = (int64_t)c->d * c->D * c->D * c->D;
+    CTM_HIP(hipMemcpyAsync(c->A, A_dev, dA * sizeof(double), hipMemcpyDeviceToDevice, s));
+    CTM_HIP(hipMemcpyAsync(c->G, G_dev, (size_t)c->nmax * c->chi * sizeof(double),
+                           hipMemcpyDeviceToDevice, s));
+    launch_symmetry_defect(s, c->A, c->d, c->D, c->dev_small);
+    double sd[2];
+    CTM_HIP(hipMemcpyAsync(sd, c->dev_small, sizeof(sd), hipMemcpyDeviceToHost, s));
+    CTM_HIP(hipStreamSynchronize(s));
+    if (!(sd[1] > 0.0) || !std::isfinite(sd[0]) || !std::isfinite(sd[1])) {
+      c->err = "site tensor is zero or not finite";
+      return CTM_ENONFINITE;
+    }
+    if (std::sqrt(sd[0]) > 1e-12 * std::sqrt(sd[1])) {
+      c->err = "site tensor is not C3v-symmetric: ||A - sym(A)|| / ||A|| = " +
+               std::to_string(std::sqrt(sd[0] / sd[1]));
+      return CTM_ENOTSYM;
+    }
+    launch_double_layer(s, c->A, c->d, c->D, c->a);
+    launch_init_env(s, c->D, c->C, c->T);
+    CTM_HIP(hipMemsetAsync(c->flag, 0, sizeof(int), s));
+    CTM_HIP(hipStreamSynchronize(s));
+    c->chi_c = 1;
+    c->steps = 0;
+    c->p_rows = 0;
+    return CTM_OK;
+  });
+  if (rc != CTM_OK) {
+    g_error = "ctm_init: " + c->err;
+    return rc;
+  }
+  *out = c.release();
+  return CTM_OK;
+}
+
+int ctm_step(ctm_ctx* c, int n_steps, double* delta_host) {
+  return guarded(c, [&]() { return do_steps(c, n_steps, delta_host); });
+}
+
+int ctm_converge(ctm_ctx* c, double tol, int max_steps, int n_check, int* steps_host,
+                 double* delta_host) {
+  return guarded(c, [&]() -> int {
+    if (max_steps < 0 || n_check < 1) throw std::invalid_argument("max_steps < 0 or n_check < 1");
+    int taken = 0;
+    double delta = std::numeric_limits<double>::infinity();
+    int rc = CTM_OK;
+    while (taken < max_steps) {
+      const int k = std::min(n_check, max_steps - taken);
+      rc = do_steps(c, k, &delta);
+      taken += k;
+      if (rc != CTM_OK) break;
+      if (delta < tol) break;
+    }
+    if (steps_host) *steps_host = taken;
+    if (delta_host) *delta_host = delta;
+    if (rc != CTM_OK) return rc;
+    if (!(delta < tol)) {
+      c->err = "tolerance not reached in max_steps";
+      return CTM_ENOTCONV;
+    }
+    return CTM_OK;
+  });
+}
+
+int ctm_energy(ctm_ctx* c, const double* h_host, double* e_host, double* rho_host) {
+  return guarded(c, [&]() -> int {
+    if (!h_host) throw std::invalid_argument("null operator");
+    return do_energy(c, h_host, e_host, rho_host);
+  });
+}
+
+int ctm_spectrum(ctm_ctx* c, double* s_host, int* n_host) {
+  return guarded(c, [&]() -> int {
+    if (!s_host) throw std::invalid_argument("null output");
+    std::vector<double> sp = current_spectrum(c);
+    std::memcpy(s_host, sp.data(), sp.size() * sizeof(double));
+    if (n_host) *n_host = c->chi_c;
+    return CTM_OK;
+  });
+}
+
+int ctm_query(const ctm_ctx* c, int* chi_c, int* steps, int* p_rows) {
+  if (!c) {
+    g_error = "null context";
+    return CTM_EINVAL;
+  }
+  if (chi_c) *chi_c = c->chi_c;
+  if (steps) *steps = c->steps;
+  if (p_rows) *p_rows = c->p_rows;
+  return CTM_OK;
+}
+
+int ctm_get_env(ctm_ctx* c, double* C_dev, double* T_dev, double* P_dev) {
+  return guarded(c, [&]() -> int {
+    hipStream_t s = c->stream;
+    const size_t x = c->chi_c;
+    if (C_dev) CTM_HIP(hipMemcpyAsync(C_dev, c->C, x * x * 8, hipMemcpyDeviceToDevice, s));
+    if (T_dev) CTM_HIP(hipMemcpyAsync(T_dev, c->T, x * c->D2 * x * 8, hipMemcpyDeviceToDevice, s));
+    if (P_dev && c->p_rows > 0)
+      CTM_HIP(hipMemcpyAsync(P_dev, c->P, (size_t)c->p_rows * c->chi * 8, hipMemcpyDeviceToDevice, s));
+    return CTM_OK;
+  });
+}
+
+int ctm_set_env(ctm_ctx* c, int chi_c, const double* C_dev, const double* T_dev, int p_rows,
+                const double* P_dev) {
+  return guarded(c, [&]() -> int {
+    if (chi_c < 1 || chi_c > c->chi || !C_dev || !T_dev || p_rows < 0 || p_rows > c->nmax ||
+        (p_rows > 0 && !P_dev))
+      throw std::invalid_argument("ctm_set_env: bad arguments");
+    hipStream_t s = c->stream;
+    const size_t x = chi_c;
+    CTM_HIP(hipMemcpyAsync(c->C, C_dev, x * x * 8, hipMemcpyDeviceToDevice, s));
+    CTM_HIP(hipMemcpyAsync(c->T, T_dev, x * c->D2 * x * 8, hipMemcpyDeviceToDevice, s));
+    if (p_rows > 0)
+      CTM_HIP(hipMemcpyAsync(c->P, P_dev, (size_t)p_rows * c->chi * 8, hipMemcpyDeviceToDevice, s));
+    c->chi_c = chi_c;
+    c->p_rows = p_rows;
+    c->spec_step = -1;
+    return CTM_OK;
+  });
+}
+
+int ctm_set_precision(ctm_ctx* c, int prec) {
+  return guarded(c, [&]() -> int {
+    if (prec < CTM_PREC_FP64 || prec > CTM_PREC_BF16) throw std::invalid_argument("bad precision");
+    c->prec = to_dtype(prec);
+    c->cfg.prec = prec;
+    return CTM_OK;
+  });
+}
+
+void ctm_free(ctm_ctx* c) { delete c; }
+
+const char* ctm_last_error(const ctm_ctx* c) {
+  if (!c) return g_error.c_str();
+  return c->err.c_str();
+}
+
+}  // extern "C"

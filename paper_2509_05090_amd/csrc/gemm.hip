@@ -1,0 +1,389 @@
+// MFMA matrix-product kernels for gfx950.
+//
+// One templated kernel serves FP64 (v_mfma_f64_16x16x4), FP32
+// (v_mfma_f32_16x16x4) and BF16 (v_mfma_f32_16x16x32_bf16, FP32 accumulate).
+// A workgroup of four 64-wide wavefronts computes a BM x BN tile; operands
+// are staged through LDS in k-chunks of 128 bytes per row (double-buffered),
+// with 16 bytes of padding so that the 16-lane row reads of the MFMA operand
+// fetch hit distinct banks.  Within a chunk the four 16-lane groups of a
+// wavefront each own a contiguous quarter of the k range, so every lane
+// fetches its operand bytes with 16-byte LDS reads.
+#include "gemm.hpp"
+
+namespace ctm {
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+template <typename E> struct Mfma;
+
+template <> struct Mfma<double> {
+  using acc_t = double;
+  using accv = d4v;
+  static constexpr int KPL = 1;  // operand elements per lane per instruction
+  // Result layout: lane (grp, r16), register r holds row 4*r + grp (rows
+  // interleaved across the four 16-lane groups), column r16.
+  static constexpr bool ROWS_INTERLEAVED = true;
+  __device__ static inline accv mma(const double* a, const double* b, accv c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], b[0], c, 0, 0, 0);
+  }
+};
+
+template <> struct Mfma<float> {
+  using acc_t = float;
+  using accv = f4v;
+  static constexpr int KPL = 1;
+  // Result layout: lane (grp, r16), register r holds row 4*grp + r, column r16.
+  static constexpr bool ROWS_INTERLEAVED = false;
+  __device__ static inline accv mma(const float* a, const float* b, accv c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], b[0], c, 0, 0, 0);
+  }
+};
+
+template <> struct Mfma<bf16> {
+  using acc_t = float;
+  using accv = f4v;
+  static constexpr int KPL = 8;
+  static constexpr bool ROWS_INTERLEAVED = false;
+  __device__ static inline accv mma(const bf16* a, const bf16* b, accv c) {
+    bf16x8 av, bv;
+    __builtin_memcpy(&av, a, 16);
+    __builtin_memcpy(&bv, b, 16);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c, 0, 0, 0);
+  }
+};
+
+struct GemmArgs {
+  int M, N, K;
+  const void* A;
+  int64_t lda, sA0, sA1;
+  const void* B;
+  int64_t ldb, sB0, sB1;
+  void* C;
+  int64_t ldc, sC0, sC1;
+  int nb1;
+  int tiles_m, tiles_n;
+  int kchunk;
+  double alpha, beta;
+};
+
+template <typename E> __device__ inline E zero_of() { return E(0); }
+template <> __device__ inline bf16 zero_of<bf16>() { return (bf16)0.0f; }
+
+// Workgroup -> (tile, batch).  Workgroups are dispatched round-robin over the
+// 8 XCDs; this order gives each XCD a contiguous range of tiles, so the
+// column tiles that re-read one row panel of A share an L2.
+__device__ inline int xcd_linear(int x, int nblk) {
+  const int per = nblk / 8, rem = nblk % 8, xcd = x % 8, slot = x / 8;
+  return xcd < rem ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
+}
+
+template <typename E, bool AT, bool BT, int BM, int BN, int WM, int WN, bool SPLIT>
+__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
+  using MF = Mfma<E>;
+  using acc_t = typename MF::acc_t;
+  using accv = typename MF::accv;
+  constexpr int NT = 256;
+  constexpr int BK = 128 / (int)sizeof(E);
+  constexpr int LDK = BK + 16 / (int)sizeof(E);
+  constexpr int FM = BM / (16 * WM), FN = BN / (16 * WN);
+  constexpr int KG = BK / 4;
+  constexpr int STEPS = KG / MF::KPL;
+  constexpr int EA = BM * BK / NT, EB = BN * BK / NT;
+  static_assert(BM % (16 * WM) == 0 && BN % (16 * WN) == 0 && WM * WN == 4, "tile");
+  static_assert(EA * NT == BM * BK && EB * NT == BN * BK, "load split");
+
+  __shared__ __attribute__((aligned(16))) E As[2][BM * LDK];
+  __shared__ __attribute__((aligned(16))) E Bs[2][BN * LDK];
+
+  const int lin = xcd_linear(blockIdx.x, gridDim.x);
+  const int tiles = g.tiles_m * g.tiles_n;
+  const int tile = lin % tiles, batch = lin / tiles;
+  const int b0 = batch / g.nb1, b1 = batch % g.nb1;
+  const int tm = tile / g.tiles_n, tn = tile % g.tiles_n;
+  const int m0 = tm * BM, n0 = tn * BN;
+  const E* __restrict__ A = (const E*)g.A + b0 * g.sA0 + b1 * g.sA1;
+  const E* __restrict__ B = (const E*)g.B + b0 * g.sB0 + b1 * g.sB1;
+  const int kbeg = blockIdx.y * g.kchunk;
+  const int kend = min(g.K, kbeg + g.kchunk);
+  const int nk = kend > kbeg ? (int)cdiv(kend - kbeg, BK) : 0;
+
+  E ra[EA], rb[EB];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < EA; ++i) {
+      const int e = threadIdx.x + i * NT;
+      const int mm = AT ? e % BM : e / BK, kk = AT ? e / BM : e % BK;
+      const int gm = m0 + mm, gk = k0 + kk;
+      E v = zero_of<E>();
+      if (gm < g.M && gk < kend)
+        v = AT ? A[(int64_t)gk * g.lda + gm] : A[(int64_t)gm * g.lda + gk];
+      ra[i] = v;
+    }
+#pragma unroll
+    for (int i = 0; i < EB; ++i) {
+      const int e = threadIdx.x + i * NT;
+      const int nn = BT ? e / BK : e % BN, kk = BT ? e % BK : e / BN;
+      const int gn = n0 + nn, gk = k0 + kk;
+      E v = zero_of<E>();
+      if (gn < g.N && gk < kend)
+        v = BT ? B[(int64_t)gn * g.ldb + gk] : B[(int64_t)gk * g.ldb + gn];
+      rb[i] = v;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < EA; ++i) {
+      const int e = threadIdx.x + i * NT;
+      const int mm = AT ? e % BM : e / BK, kk = AT ? e / BM : e % BK;
+      As[buf][mm * LDK + kk] = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < EB; ++i) {
+      const int e = threadIdx.x + i * NT;
+      const int nn = BT ? e / BK : e % BN, kk = BT ? e % BK : e / BN;
+      Bs[buf][nn * LDK + kk] = rb[i];
+    }
+  };
+
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int wm = wid % WM, wn = wid / WM;
+  const int r16 = lane & 15, grp = lane >> 4;
+  accv acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = accv{0, 0, 0, 0};
+
+  if (nk > 0) {
+    load(kbeg);
+    store(0);
+    __syncthreads();
+  }
+  for (int c = 0; c < nk; ++c) {
+    const int cur = c & 1;
+    if (c + 1 < nk) load(kbeg + (c + 1) * BK);
+    E af[FM][KG], bfr[FN][KG];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+      __builtin_memcpy(&af[i][0], &As[cur][(wm * FM * 16 + i * 16 + r16) * LDK + grp * KG], 32);
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+      __builtin_memcpy(&bfr[j][0], &Bs[cur][(wn * FN * 16 + j * 16 + r16) * LDK + grp * KG], 32);
+#pragma unroll
+    for (int s = 0; s < STEPS; ++s)
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+          acc[i][j] = MF::mma(&af[i][s * MF::KPL], &bfr[j][s * MF::KPL], acc[i][j]);
+    if (c + 1 < nk) store(cur ^ 1);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int rr = MF::ROWS_INTERLEAVED ? r * 4 + grp : grp * 4 + r;
+        const int row = m0 + wm * FM * 16 + i * 16 + rr;
+        const int col = n0 + wn * FN * 16 + j * 16 + r16;
+        if (row < g.M && col < g.N) {
+          if constexpr (SPLIT) {
+            acc_t* W = (acc_t*)g.C + (int64_t)blockIdx.y * g.M * g.N;
+            W[(int64_t)row * g.N + col] = acc[i][j][r];
+          } else {
+            E* C = (E*)g.C + b0 * g.sC0 + b1 * g.sC1;
+            double v = g.alpha * (double)acc[i][j][r];
+            if (g.beta != 0.0) v += g.beta * to_f64(C[(int64_t)row * g.ldc + col]);
+            C[(int64_t)row * g.ldc + col] = from_f64<E>(v);
+          }
+        }
+      }
+}
+
+constexpr int RED_THREADS = 256;
+constexpr int RED_MAX_BLOCKS = 1024;
+
+int sumsq_blocks(int M, int N) {
+  int64_t mn = (int64_t)M * N;
+  return (int)std::min<int64_t>(RED_MAX_BLOCKS, std::max<int64_t>(1, cdiv(mn, RED_THREADS * 4)));
+}
+
+// C = alpha * sum_s W[s] + beta * C, summed in a fixed order; optional
+// per-block sums of squares of the result.
+template <typename Acc, typename TC>
+__global__ __launch_bounds__(RED_THREADS) void splitk_reduce(const Acc* __restrict__ W, int S, int M,
+                                                          int N, TC* C, int64_t ldc, double alpha,
+                                                          double beta, double* sumsq) {
+  const int64_t mn = (int64_t)M * N;
+  double ss = 0.0;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < mn;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    double v = 0.0;
+    for (int s = 0; s < S; ++s) v += (double)W[s * mn + idx];
+    const int64_t row = idx / N, col = idx % N;
+    TC* dst = C + row * ldc + col;
+    v *= alpha;
+    if (beta != 0.0) v += beta * to_f64(*dst);
+    *dst = from_f64<TC>(v);
+    ss += v * v;
+  }
+  if (sumsq) {
+    __shared__ double red[RED_THREADS / 64];
+    for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = ss;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int w = 0; w < RED_THREADS / 64; ++w) t += red[w];
+      sumsq[blockIdx.x] = t;
+    }
+  }
+}
+
+namespace {
+
+struct TileCfg {
+  int BM, BN;
+};
+constexpr TileCfg CFGS[3] = {{64, 64}, {64, 48}, {32, 32}};
+
+template <typename E, bool AT, bool BT, bool SPLIT>
+void launch_cfg(int cfg, dim3 grid, hipStream_t s, const GemmArgs& a) {
+  switch (cfg) {
+    case 0: gemm_kernel<E, AT, BT, 64, 64, 2, 2, SPLIT><<<grid, 256, 0, s>>>(a); break;
+    case 1: gemm_kernel<E, AT, BT, 64, 48, 4, 1, SPLIT><<<grid, 256, 0, s>>>(a); break;
+    default: gemm_kernel<E, AT, BT, 32, 32, 2, 2, SPLIT><<<grid, 256, 0, s>>>(a); break;
+  }
+}
+
+template <typename E, bool SPLIT>
+void launch_trans(bool at, bool bt, int cfg, dim3 grid, hipStream_t s, const GemmArgs& a) {
+  if (!at && !bt) launch_cfg<E, false, false, SPLIT>(cfg, grid, s, a);
+  else if (!at && bt) launch_cfg<E, false, true, SPLIT>(cfg, grid, s, a);
+  else if (at && !bt) launch_cfg<E, true, false, SPLIT>(cfg, grid, s, a);
+  else launch_cfg<E, true, true, SPLIT>(cfg, grid, s, a);
+}
+
+template <typename E>
+void launch_any(bool split, bool at, bool bt, int cfg, dim3 grid, hipStream_t s, const GemmArgs& a) {
+  if (split) launch_trans<E, true>(at, bt, cfg, grid, s, a);
+  else launch_trans<E, false>(at, bt, cfg, grid, s, a);
+}
+
+template <typename Acc>
+void launch_reduce(DType out, const Acc* W, int S, int M, int N, void* C, int64_t ldc,
+                   double alpha, double beta, double* sumsq, hipStream_t s) {
+  const int blocks = sumsq_blocks(M, N);
+  switch (out) {
+    case DType::F64:
+      splitk_reduce<Acc, double><<<blocks, RED_THREADS, 0, s>>>(W, S, M, N, (double*)C, ldc, alpha,
+                                                                beta, sumsq);
+      break;
+    case DType::F32:
+      splitk_reduce<Acc, float><<<blocks, RED_THREADS, 0, s>>>(W, S, M, N, (float*)C, ldc, alpha,
+                                                               beta, sumsq);
+      break;
+    case DType::BF16:
+      splitk_reduce<Acc, bf16><<<blocks, RED_THREADS, 0, s>>>(W, S, M, N, (bf16*)C, ldc, alpha,
+                                                              beta, sumsq);
+      break;
+  }
+}
+
+int pick_cfg(int M, int N) {
+  int best = 0;
+  int64_t best_area = INT64_MAX;
+  for (int c = 0; c < 3; ++c) {
+    const int64_t area = cdiv(M, CFGS[c].BM) * CFGS[c].BM * cdiv(N, CFGS[c].BN) * CFGS[c].BN;
+    if (area < best_area) {
+      best_area = area;
+      best = c;
+    }
+  }
+  return best;
+}
+
+}  // namespace
+
+constexpr int MAX_SPLIT = 16;
+
+size_t gemm_scratch_bytes(DType e, int M, int N) {
+  const size_t acc = e == DType::F64 ? 8 : 4;
+  return (size_t)MAX_SPLIT * M * N * acc;
+}
+
+void gemm(hipStream_t s, DType e, int M, int N, int K, const Operand& A, const Operand& B,
+          const Output& C, int nb0, int nb1, double alpha, double beta, const Scratch& ws,
+          int ksplit, double* sumsq) {
+  if (M <= 0 || N <= 0 || nb0 <= 0 || nb1 <= 0) return;
+  const int cfg = pick_cfg(M, N);
+  const int BM = CFGS[cfg].BM, BN = CFGS[cfg].BN;
+  const int BK = 128 / (int)dtype_size(e);
+  GemmArgs a{};
+  a.M = M;
+  a.N = N;
+  a.K = K;
+  a.A = A.p;
+  a.lda = A.ld;
+  a.sA0 = A.s0;
+  a.sA1 = A.s1;
+  a.B = B.p;
+  a.ldb = B.ld;
+  a.sB0 = B.s0;
+  a.sB1 = B.s1;
+  a.C = C.p;
+  a.ldc = C.ld;
+  a.sC0 = C.s0;
+  a.sC1 = C.s1;
+  a.nb1 = nb1;
+  a.tiles_m = (int)cdiv(M, BM);
+  a.tiles_n = (int)cdiv(N, BN);
+  a.alpha = alpha;
+  a.beta = beta;
+  const int64_t tiles = (int64_t)a.tiles_m * a.tiles_n;
+  const int64_t nbatch = (int64_t)nb0 * nb1;
+  const bool batched = nbatch > 1;
+  const DType acc_t = e == DType::F64 ? DType::F64 : DType::F32;
+  bool split = ksplit > 1 || C.t != e || sumsq != nullptr;
+  if (!batched && ksplit == 0 && tiles < 1024) {
+    const int want = (int)std::min<int64_t>(MAX_SPLIT, std::max<int64_t>(1, 1024 / tiles));
+    const int maxk = (int)std::max<int64_t>(1, cdiv(K, 4 * BK));
+    const int fit = (int)std::max<int64_t>(
+        1, (int64_t)(ws.bytes / ((size_t)M * N * dtype_size(acc_t))));
+    ksplit = std::min(std::min(want, maxk), fit);
+    if (ksplit > 1) split = true;
+  }
+  if (ksplit < 1) ksplit = 1;
+  if (split && batched)
+    throw std::invalid_argument("gemm: split-K output or a foreign output type needs an unbatched product");
+  if (split) {
+    const size_t need = (size_t)ksplit * M * N * dtype_size(acc_t);
+    if (need > ws.bytes) throw std::invalid_argument("gemm: scratch too small");
+  }
+  a.kchunk = split ? (int)std::max<int64_t>(BK, cdiv(cdiv(K, ksplit), BK) * BK) : std::max(K, 1);
+  if (split) {
+    ksplit = (int)std::max<int64_t>(1, cdiv(K, a.kchunk));
+    a.C = ws.p;
+  }
+  dim3 grid((unsigned)(tiles * nbatch), split ? ksplit : 1);
+  switch (e) {
+    case DType::F64: launch_any<double>(split, A.trans, B.trans, cfg, grid, s, a); break;
+    case DType::F32: launch_any<float>(split, A.trans, B.trans, cfg, grid, s, a); break;
+    case DType::BF16: launch_any<bf16>(split, A.trans, B.trans, cfg, grid, s, a); break;
+  }
+  CTM_LAUNCHED();
+  if (split) {
+    if (acc_t == DType::F64)
+      launch_reduce<double>(C.t, (const double*)ws.p, ksplit, M, N, C.p, C.ld, alpha, beta, sumsq, s);
+    else
+      launch_reduce<float>(C.t, (const float*)ws.p, ksplit, M, N, C.p, C.ld, alpha, beta, sumsq, s);
+    CTM_LAUNCHED();
+  }
+}
+
+}  // namespace ctm

@@ -1,0 +1,101 @@
+// C entry points of the step's building blocks (see include/ctm_kernels.h).
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "ctm.h"
+#include "ctm_kernels.h"
+#include "gemm.hpp"
+#include "qr.hpp"
+
+using namespace ctm;
+
+namespace ctm {
+void set_global_error(const std::string& s);
+}
+
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  explicit DevBuf(size_t bytes) { CTM_HIP(hipMalloc(&p, bytes ? bytes : 8)); }
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+};
+
+__global__ void copy_upper_kernel(const double* M, int ld, int k, double* R) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= k * k) return;
+  const int r = i / k, c = i % k;
+  R[i] = c >= r ? M[(size_t)r * ld + c] : 0.0;
+}
+
+}  // namespace
+
+extern "C" int ctm_gemm(int prec, int M, int N, int K, const void* A, int64_t lda, int transA,
+                        int64_t sA0, int64_t sA1, const void* B, int64_t ldb, int transB,
+                        int64_t sB0, int64_t sB1, void* C, int64_t ldc, int ctype, int64_t sC0,
+                        int64_t sC1, int nb0, int nb1, double alpha, double beta, int ksplit,
+                        void* stream) {
+  if (prec < 0 || prec > 2 || ctype < 0 || ctype > 2 || M < 0 || N < 0 || K < 1 || nb0 < 1 ||
+      nb1 < 1 || !A || !B || !C || ksplit < 0) {
+    set_global_error("ctm_gemm: bad arguments");
+    return CTM_EINVAL;
+  }
+  try {
+    const DType e = (DType)prec;
+    const size_t wsb = (ksplit > 1 || nb0 * nb1 == 1) ? gemm_scratch_bytes(e, M, N) : 0;
+    DevBuf ws(wsb);
+    gemm((hipStream_t)stream, e, M, N, K, Operand{A, lda, transA != 0, sA0, sA1},
+         Operand{B, ldb, transB != 0, sB0, sB1}, Output{C, ldc, (DType)ctype, sC0, sC1}, nb0, nb1,
+         alpha, beta, Scratch{ws.p, wsb}, ksplit);
+    CTM_HIP(hipStreamSynchronize((hipStream_t)stream));
+    return CTM_OK;
+  } catch (const DeviceError& ex) {
+    set_global_error(ex.what());
+    return CTM_EDEVICE;
+  } catch (const std::exception& ex) {
+    set_global_error(ex.what());
+    return CTM_EINVAL;
+  }
+}
+
+extern "C" int ctm_qr(const double* M_dev, int n, int k, double* Q_dev, double* R_dev,
+                      void* stream) {
+  if (!M_dev || !Q_dev || k < 1 || n < k) {
+    set_global_error("ctm_qr: bad arguments");
+    return CTM_EINVAL;
+  }
+  try {
+    hipStream_t s = (hipStream_t)stream;
+    DevBuf Mw((size_t)n * k * 8), Y((size_t)n * k * 8), tau((size_t)k * 8),
+        Tf((size_t)cdiv(k, QR_NB) * QR_NB * QR_NB * 8), W((size_t)QR_NB * k * 8),
+        W2((size_t)QR_NB * k * 8), ws(gemm_scratch_bytes(DType::F64, QR_NB, k));
+    QrWork w;
+    w.Y = (double*)Y.p;
+    w.tau = (double*)tau.p;
+    w.Tf = (double*)Tf.p;
+    w.W = (double*)W.p;
+    w.W2 = (double*)W2.p;
+    w.ws = Scratch{ws.p, gemm_scratch_bytes(DType::F64, QR_NB, k)};
+    CTM_HIP(hipMemcpyAsync(Mw.p, M_dev, (size_t)n * k * 8, hipMemcpyDeviceToDevice, s));
+    householder_qr(s, (double*)Mw.p, k, n, k, w);
+    householder_form_q(s, w, n, k, Q_dev, k);
+    if (R_dev) {
+      copy_upper_kernel<<<(unsigned)cdiv((int64_t)k * k, 256), 256, 0, s>>>((const double*)Mw.p, k,
+                                                                            k, R_dev);
+      CTM_LAUNCHED();
+    }
+    CTM_HIP(hipStreamSynchronize(s));
+    return CTM_OK;
+  } catch (const DeviceError& ex) {
+    set_global_error(ex.what());
+    return CTM_EDEVICE;
+  } catch (const std::exception& ex) {
+    set_global_error(ex.what());
+    return CTM_EINVAL;
+  }
+}

@@ -1,0 +1,116 @@
+"""GPU checks of the building blocks through the C interface: the MFMA
+matrix products (FP64, FP32, BF16 with FP32 accumulation; all operand
+layouts, batches, split-K, ragged tiles) and the blocked Householder QR."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2509_05090_amd import ctm
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda")
+TDT = {0: torch.float64, 1: torch.float32, 2: torch.bfloat16}
+
+
+def _rng(seed):
+    return np.random.default_rng(seed)
+
+
+def _stored(x, prec):
+    """Host copy of the values a device operand of type prec actually holds."""
+    return torch.tensor(x).to(TDT[prec]).double().numpy()
+
+
+def run_gemm(M, N, K, prec, ta, tb, seed, ksplit=0, alpha=1.0, beta=0.0, ctype=None):
+    r = _rng(seed)
+    ctype = prec if ctype is None else ctype
+    A = r.standard_normal((K, M) if ta else (M, K))
+    B = r.standard_normal((N, K) if tb else (K, N))
+    C0 = r.standard_normal((M, N))
+    Ad = torch.tensor(A, device=DEV).to(TDT[prec])
+    Bd = torch.tensor(B, device=DEV).to(TDT[prec])
+    Cd = torch.tensor(C0, device=DEV).to(TDT[ctype])
+    ctm.gemm(Ad, Bd, Cd, M, N, K, lda=M if ta else K, ldb=K if tb else N, ldc=N, transA=ta,
+             transB=tb, alpha=alpha, beta=beta, prec=prec, ksplit=ksplit)
+    torch.cuda.synchronize()
+    Ah, Bh = _stored(A, prec), _stored(B, prec)
+    opA = Ah.T if ta else Ah
+    opB = Bh.T if tb else Bh
+    ref = alpha * opA @ opB + beta * _stored(C0, ctype)
+    scale = alpha * np.abs(opA) @ np.abs(opB) + abs(beta) * np.abs(C0) + 1e-300
+    err = np.abs(Cd.double().cpu().numpy() - ref) / scale
+    return err.max()
+
+
+TOL = {0: 1e-14, 1: 2e-6, 2: 2e-6}
+TOL_OUT = {0: 1e-14, 1: 2e-6, 2: 5e-3}  # output stored in the operand type
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("ta,tb", [(False, False), (False, True), (True, False), (True, True)])
+@pytest.mark.parametrize("M,N,K", [(1, 1, 1), (17, 5, 3), (100, 37, 45), (130, 144, 300),
+                                   (64, 48, 129), (33, 200, 1000)])
+def test_gemm_layouts(prec, ta, tb, M, N, K):
+    seed = M * 7919 + N * 31 + K + prec * 1000003 + 2 * ta + tb
+    err = run_gemm(M, N, K, prec, ta, tb, seed)
+    # no split and same output type -> output rounded to the operand type
+    assert err < max(TOL[prec], TOL_OUT[prec]), err
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_gemm_split_k_fp64_output(prec):
+    err = run_gemm(70, 48, 5000, prec, False, False, 11, ksplit=7, ctype=0)
+    assert err < TOL[prec] * 10, err
+    err = run_gemm(300, 144, 5184, prec, False, True, 12, ksplit=0, ctype=0)
+    assert err < TOL[prec] * 10, err
+
+
+def test_gemm_alpha_beta_in_place():
+    err = run_gemm(200, 100, 16, 0, False, False, 13, ksplit=1, alpha=-1.0, beta=1.0)
+    assert err < 1e-14
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_gemm_two_level_batch(prec):
+    """C[b0][b1] = A[b0] B[b1] with independent strides, ragged 36-wide tiles."""
+    r = _rng(21)
+    nb0, nb1, M, N, K = 3, 4, 40, 36, 36
+    A = r.standard_normal((nb0, K, M))        # transposed operand, batched over b0
+    B = r.standard_normal((nb1, K, N))        # batched over b1
+    Ad = torch.tensor(A, device=DEV).to(TDT[prec])
+    Bd = torch.tensor(B, device=DEV).to(TDT[prec])
+    Cd = torch.zeros((nb0, nb1, M, N), device=DEV, dtype=TDT[prec])
+    ctm.gemm(Ad, Bd, Cd, M, N, K, lda=M, ldb=N, ldc=N, transA=True, prec=prec, batch=(nb0, nb1),
+             sA=(K * M, 0), sB=(0, K * N), sC=(nb1 * M * N, M * N))
+    torch.cuda.synchronize()
+    Ah, Bh = _stored(A, prec), _stored(B, prec)
+    ref = np.einsum("akm,bkn->abmn", Ah, Bh)
+    scale = np.einsum("akm,bkn->abmn", np.abs(Ah), np.abs(Bh))
+    err = np.abs(Cd.double().cpu().numpy() - ref) / scale
+    assert err.max() < max(TOL[prec], TOL_OUT[prec]), err.max()
+
+
+@pytest.mark.parametrize("n,k", [(16, 16), (40, 16), (200, 37), (1024, 64), (1600, 100), (5184, 144)])
+def test_householder_qr(n, k):
+    M = _rng(n + k).standard_normal((n, k))
+    Q, R = ctm.qr(torch.tensor(M, device=DEV))
+    torch.cuda.synchronize()
+    Q, R = Q.cpu().numpy(), R.cpu().numpy()
+    assert np.abs(np.tril(R, -1)).max() == 0.0
+    assert np.abs(Q.T @ Q - np.eye(k)).max() < 1e-13
+    assert np.abs(Q @ R - M).max() < 1e-13 * np.abs(M).max() * np.sqrt(n)
+    # same triangular factor as LAPACK up to row signs, LAPACK's sign convention
+    Rl = np.linalg.qr(M, mode="r")
+    assert np.allclose(np.abs(np.diag(R)), np.abs(np.diag(Rl)), rtol=1e-12)
+
+
+def test_householder_qr_rank_deficient():
+    """A matrix of rank 1 (the product-state case) must still give an
+    orthonormal Q and Q R = M."""
+    r = _rng(5)
+    u, v = r.standard_normal((300, 1)), r.standard_normal((1, 20))
+    M = u @ v
+    Q, R = ctm.qr(torch.tensor(M, device=DEV))
+    Q, R = Q.cpu().numpy(), R.cpu().numpy()
+    assert np.abs(Q.T @ Q - np.eye(20)).max() < 1e-13
+    assert np.abs(Q @ R - M).max() < 1e-12 * np.abs(M).max()
