@@ -48,9 +48,13 @@ enum {
 
 /* Projector of the CTMRG step (Sec. II.B).
  * CTM_PROJ_QR:  thin QR of the chi_c D^2 x chi reduced corner M = Ct P_prev
- *               (Fig. 3d); Q is the new isometry.  One sweep of orthogonal
- *               iteration per step: at a fixed point Q spans a dominant
- *               eigenspace of the enlarged corner Ct.
+ *               (Fig. 3d), Q1 R = M; the isometry is Q = Q1 gs(Q1^T P_prev),
+ *               gs(X) the Gram-Schmidt basis of X's columns (QR with positive
+ *               diagonal), which ties the basis inside span(Q1) to P_prev
+ *               (the paper fixes none).  One sweep of orthogonal iteration
+ *               per step: at a fixed point Q spans a dominant eigenspace of
+ *               the enlarged corner Ct.  The first projector of an n-row
+ *               corner is gs(first n rows of G).
  * CTM_PROJ_EVD: eigenvectors of Ct of the chi largest |eigenvalues|
  *               (Fig. 3c).  Reserved; not implemented by this library yet. */
 typedef enum { CTM_PROJ_QR = 0, CTM_PROJ_EVD = 1 } ctm_proj;
@@ -91,7 +95,8 @@ int ctm_init(ctm_ctx **out, const ctm_config *cfg, const double *A_dev, const do
  * Ct[(alpha,k),(beta,l)] = sum T[alpha,i,gamma] C[gamma,delta] T[beta,j,delta]
  * a[i,j,m] a[m,k,l]; projector Q (identity while chi_c D^2 <= chi);
  * C' = Q^T Ct Q symmetrized and T' = Q^T (T b) Q, both Frobenius-normalized.
- * Column signs of Q follow the previous projector.  Nothing is synchronized
+ * The basis of Q follows the previous projector (see CTM_PROJ_QR), so a
+ * converged environment is stationary element by element.  Nothing is synchronized
  * unless delta_host is non-null; then it receives the change of the
  * normalized corner spectrum across the last step (INFINITY if undefined).
  * Errors: CTM_EINVAL, CTM_ENONFINITE, CTM_EDEVICE. */
@@ -137,6 +142,27 @@ int ctm_set_env(ctm_ctx *c, int chi_c, const double *C_dev, const double *T_dev,
 /* Switch the contraction arithmetic of an existing context (for a precision
  * ladder: low precision far from convergence, FP64 near it). */
 int ctm_set_precision(ctm_ctx *c, int prec);
+
+/* Stages of a step timed by ctm_profile_read(). */
+enum {
+  CTM_STAGE_CORNER = 0,    /* enlarged corner (Fig. 3a,c): products 1-4 */
+  CTM_STAGE_PROJECTOR = 1, /* reduced corner M = Ct P_prev, QR, basis (Fig. 3d) */
+  CTM_STAGE_RENORM_C = 2,  /* C' = Q^T Ct Q, symmetrize, normalize (Fig. 3a) */
+  CTM_STAGE_RENORM_T = 3,  /* T' = Q^T (T b) Q, normalize (Fig. 3b) */
+  CTM_STAGE_BIG_GEMM = 4,  /* the (chi_c D^2) x chi x (chi_c D^2) matrix-core kernels
+                              inside stages 0-3 (kernel time only) */
+  CTM_NSTAGES = 5
+};
+
+/* Start (enable = 1) or stop (0) recording HIP events around every stage
+ * of ctm_step on the context's stream; starting resets the totals. */
+int ctm_profile(ctm_ctx *c, int enable);
+
+/* Totals since the last reset (synchronizes): ms_host[CTM_NSTAGES] elapsed
+ * GPU time, launches_host[CTM_NSTAGES] timed intervals, flops_host[0] the
+ * algorithmic flop count of the CTM_STAGE_BIG_GEMM kernels (2 M N K each).
+ * Any pointer may be null. */
+int ctm_profile_read(ctm_ctx *c, double *ms_host, int64_t *launches_host, double *flops_host);
 
 /* Free a context and all its device memory (null is ignored). */
 void ctm_free(ctm_ctx *c);

@@ -120,7 +120,17 @@ def order_by_magnitude(lam: np.ndarray) -> np.ndarray:
     return np.lexsort((idx, -lam, -np.abs(lam)))
 
 
-def qr_projector(Ct, chi, P_prev, G, rr_gauge=False):
+def align_basis(Q: np.ndarray, P_prev: np.ndarray) -> np.ndarray:
+    """Basis of span(Q) tied to the previous projector: the Gram-Schmidt
+    orthonormalization (within span(Q)) of the projections of P_prev's
+    columns, Q <- Q gs(Q^T P_prev).  If span(Q) = span(P_prev) this returns
+    P_prev itself, so a converged projector is stationary element by
+    element; the column overlaps Q^T P_prev come out upper triangular with a
+    positive diagonal, which fixes the column signs as well."""
+    return Q @ gram_schmidt_basis(Q.T @ P_prev)
+
+
+def qr_projector(Ct, chi, P_prev, G, rr_gauge=False, gauge="align"):
     """QR-based projector (Fig. 3d).  The reduced corner is M = Ct P_prev, an
     n x chi matrix (chi D^2 x chi); its thin QR factor Q is the isometry.
 
@@ -129,6 +139,15 @@ def qr_projector(Ct, chi, P_prev, G, rr_gauge=False):
     Ct Q = Q R with Q^T Ct Q = R symmetric and triangular, hence diagonal, so
     Q spans a dominant eigenspace of Ct and the method shares the fixed point
     of the eigendecomposition-based CTMRG (Fig. 3c).
+
+    The paper fixes no basis inside span(Q).  A QR factor alone does not
+    converge element by element when Ct has eigenvalue pairs of equal
+    modulus (for a pair +-lambda one QR sweep maps the 2x2 block
+    [[a, b], [b, -a]] to [[a, -b], [-b, -a]], a two-cycle), and then P_prev no
+    longer matches the basis of the next enlarged corner.  gauge="align"
+    (default) ties the basis to P_prev with align_basis(); gauge="sign" only
+    flips column signs to follow P_prev; rr_gauge adds a Rayleigh-Ritz
+    rotation to the eigenbasis of Q^T Ct Q before the gauge step.
 
     Returns (Q, new P_prev)."""
     n = Ct.shape[0]
@@ -141,7 +160,12 @@ def qr_projector(Ct, chi, P_prev, G, rr_gauge=False):
     if rr_gauge:
         w, V = np.linalg.eigh(Q.T @ Ct @ Q)
         Q = Q @ V[:, order_by_magnitude(w)]
-    Q = align_signs(Q, P_prev)
+    if gauge == "align":
+        Q = align_basis(Q, P_prev)
+    elif gauge == "sign":
+        Q = align_signs(Q, P_prev)
+    else:
+        raise ValueError(gauge)
     return Q, Q
 
 
@@ -206,13 +230,14 @@ def spectrum_change(s, s_prev):
 class State:
     """Environment of one CTMRG run."""
 
-    def __init__(self, A, chi, G, proj="qr", rr_gauge=False):
+    def __init__(self, A, chi, G, proj="qr", rr_gauge=False, gauge="align"):
         self.A = np.asarray(A, dtype=np.float64)
         self.d, self.D = A.shape[0], A.shape[1]
         self.chi = chi
         self.G = G
         self.proj = proj
         self.rr_gauge = rr_gauge
+        self.gauge = gauge
         self.a = double_layer(self.A)
         self.C, self.T = initial_environment(self.D)
         self.P = None
@@ -221,7 +246,7 @@ class State:
 
     def projector(self, Ct, P_prev):
         if self.proj == "qr":
-            return qr_projector(Ct, self.chi, P_prev, self.G, self.rr_gauge)
+            return qr_projector(Ct, self.chi, P_prev, self.G, self.rr_gauge, self.gauge)
         if self.proj == "evd":
             return evd_projector(Ct, self.chi, P_prev)
         raise ValueError(self.proj)

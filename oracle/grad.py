@@ -48,20 +48,22 @@ def enlarged_corner(C, T, a):
     return Ct.reshape(chi * D2, chi * D2)
 
 
-def _signs(Q, P_prev):
-    s = torch.sign((P_prev * Q).sum(0)).detach()
+def gram_schmidt_basis(G):
+    """Orthonormal basis of G's columns with diag(R) > 0 (differentiable)."""
+    Q, R = torch.linalg.qr(G)
+    s = torch.sign(torch.diagonal(R)).detach()
     s[s == 0] = 1.0
-    return s
+    return Q * s
 
 
 def qr_projector(Ct, chi, P_prev):
-    """Q from the thin QR of the reduced corner Ct P_prev, column signs aligned
-    with P_prev (the sign choice is piecewise constant: no derivative)."""
+    """Q from the thin QR of the reduced corner Ct P_prev, its basis tied to
+    P_prev by Q <- Q gs(Q^T P_prev) (the oracle's default gauge)."""
     n = Ct.shape[0]
     if n <= chi:
         return torch.eye(n, dtype=DT), P_prev
     Q, _ = torch.linalg.qr(Ct @ P_prev)
-    Q = Q * _signs(Q, P_prev)
+    Q = Q @ gram_schmidt_basis(Q.T @ P_prev)
     return Q, Q
 
 

@@ -15,7 +15,9 @@
 //        enlarged corner, symmetric
 //   5. projector Q (n x chi): identity while n <= chi; else the thin QR of
 //        the reduced corner M = Ct . P_prev (n x chi, k = n), FP64 blocked
-//        Householder, column signs aligned with P_prev, P_prev <- Q
+//        Householder, Q1; its basis is tied to P_prev: Q = Q1 gs(Q1^T P_prev)
+//        with gs the Gram-Schmidt basis (QR with positive diagonal of the
+//        chi x chi overlap); P_prev <- Q
 //   6. Gm = Ct . Q                                    (n x chi, k = n)
 //   7. C' = Q^T . Gm, then (C' + C'^T)/2 / ||.||_F     (chi x chi, k = n)
 //   8. V2 = V . Q                                     (n x chi, k = n)
@@ -74,8 +76,8 @@ struct ctm_ctx {
   double *A = nullptr, *a = nullptr, *aO = nullptr, *aOr = nullptr, *G = nullptr;
   double *C = nullptr, *T = nullptr, *Cn = nullptr, *Tn = nullptr, *P = nullptr;
   // FP64 work
-  double *M = nullptr, *Q = nullptr, *Cp = nullptr, *Tp = nullptr;
-  double *sgn = nullptr, *part = nullptr, *sumsq = nullptr, *dev_small = nullptr;
+  double *M = nullptr, *Q = nullptr, *Cp = nullptr, *Tp = nullptr, *Xs = nullptr, *Xq = nullptr;
+  double *sgn = nullptr, *sumsq = nullptr, *dev_small = nullptr;
   int* flag = nullptr;
   // Intermediates; allocated with 8-byte elements so that they hold any precision.
   void *aE = nullptr, *CE = nullptr, *TE = nullptr, *PE = nullptr, *QE = nullptr;
@@ -89,6 +91,27 @@ struct ctm_ctx {
   // spectrum cache (host)
   std::vector<double> spec;
   int spec_step = -1;
+
+  // stage timing (HIP events on the stream)
+  struct TimedInterval {
+    int stage;
+    hipEvent_t begin, end;
+  };
+  bool prof_on = false, prof_active = false;
+  std::vector<hipEvent_t> event_pool;
+  size_t events_used = 0;
+  std::vector<TimedInterval> intervals;
+  double big_flops = 0.0;
+  hipEvent_t stage_open[CTM_NSTAGES] = {};
+
+  hipEvent_t next_event() {
+    if (events_used == event_pool.size()) {
+      hipEvent_t e;
+      CTM_HIP(hipEventCreate(&e));
+      event_pool.push_back(e);
+    }
+    return event_pool[events_used++];
+  }
 
   void* alloc(size_t bytes) {
     void* p = nullptr;
@@ -105,6 +128,7 @@ struct ctm_ctx {
 
   ~ctm_ctx() {
     if (stream) (void)hipStreamSynchronize(stream);
+    for (hipEvent_t e : event_pool) (void)hipEventDestroy(e);
     for (void* p : allocations) (void)hipFree(p);
   }
 };
@@ -143,11 +167,11 @@ DType to_dtype(int prec) {
   return prec == CTM_PREC_FP32 ? DType::F32 : (prec == CTM_PREC_BF16 ? DType::BF16 : DType::F64);
 }
 
-// Working-precision views of FP64 data: the FP64 buffer itself in FP64 mode,
+// View of FP64 data in arithmetic e: the FP64 buffer itself for e = F64,
 // else a converted copy in `scratch`.
-const void* as_prec(ctm_ctx* c, const double* src, void* scratch, int64_t n) {
-  if (c->prec == DType::F64) return src;
-  launch_cast(c->stream, src, scratch, c->prec, n);
+const void* as_prec(ctm_ctx* c, DType e, const double* src, void* scratch, int64_t n) {
+  if (e == DType::F64) return src;
+  launch_cast(c->stream, src, scratch, e, n);
   return scratch;
 }
 
@@ -156,6 +180,29 @@ bool read_flag(ctm_ctx* c) {
   CTM_HIP(hipMemcpyAsync(&f, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   CTM_HIP(hipStreamSynchronize(c->stream));
   return f != 0;
+}
+
+void stage_begin(ctm_ctx* c, int stage) {
+  if (!c->prof_active) return;
+  c->stage_open[stage] = c->next_event();
+  CTM_HIP(hipEventRecord(c->stage_open[stage], c->stream));
+}
+
+void stage_end(ctm_ctx* c, int stage) {
+  if (!c->prof_active) return;
+  hipEvent_t e = c->next_event();
+  CTM_HIP(hipEventRecord(e, c->stream));
+  c->intervals.push_back({stage, c->stage_open[stage], e});
+}
+
+// Events around one of the big (n x chi x n) matrix-core kernels, or null.
+const KernelEvents* big_gemm_events(ctm_ctx* c, KernelEvents& ev, double M, double N, double K) {
+  if (!c->prof_active) return nullptr;
+  ev.begin = c->next_event();
+  ev.end = c->next_event();
+  c->intervals.push_back({CTM_STAGE_BIG_GEMM, ev.begin, ev.end});
+  c->big_flops += 2.0 * M * N * K;
+  return &ev;
 }
 
 std::vector<double> current_spectrum(ctm_ctx* c) {
@@ -205,17 +252,28 @@ void enlarged_corner(ctm_ctx* c, DType e) {
        Operand{aE, D2, false, 0, (int64_t)D2 * D2}, Output{c->V, D2, e, D2 * n, n}, x, D2, 1.0,
        0.0, c->ws);
   // 3. W = V TCp^T
+  KernelEvents ev;
   gemm(s, e, (int)n, x, (int)n, Operand{c->V, n, false}, Operand{c->TCp, n, true},
-       Output{c->W, x, e}, 1, 1, 1.0, 0.0, c->ws);
+       Output{c->W, x, e}, 1, 1, 1.0, 0.0, c->ws, 0, nullptr, big_gemm_events(c, ev, n, x, n));
   // 4. Ct[(alpha,k)][(beta,l)]
   gemm(s, e, x, D2, D2, Operand{c->W, x, true, (int64_t)D2 * x, 0},
        Operand{aE, (int64_t)D2 * D2, false, 0, D2}, Output{c->Ct, D2, e, D2 * n, n}, x, D2, 1.0,
        0.0, c->ws);
 }
 
+// Gram-Schmidt basis of the columns of the k x k matrix X (QR with a
+// positive diagonal of R), into Qx.  X is overwritten.
+void gram_schmidt_small(ctm_ctx* c, double* X, int k, double* Qx) {
+  hipStream_t s = c->stream;
+  householder_qr(s, X, k, k, k, c->qr);
+  householder_form_q(s, c->qr, k, k, Qx, k);
+  launch_diag_signs(s, X, k, k, c->sgn);
+  launch_apply_signs(s, Qx, k, k, c->sgn, nullptr);
+}
+
 // Projector of the QR rule for the current Ct into c->Q (FP64, n x chi,
-// ld chi), sign-aligned with the stored P_prev (or the start projector when
-// P_prev does not match n).  If update, P_prev <- Q.
+// ld chi): thin QR of M = Ct P_prev, basis tied to P_prev (or to the start
+// projector when P_prev does not match n).  If update, P_prev <- Q.
 void qr_projector(ctm_ctx* c, DType e, bool update) {
   hipStream_t s = c->stream;
   const int chi = c->chi;
@@ -226,20 +284,28 @@ void qr_projector(ctm_ctx* c, DType e, bool update) {
       start_projector(c, n, c->P);
       c->p_rows = n;
     } else {
-      Pref = (double*)c->PE;  // 8-byte scratch of n x chi
+      Pref = (double*)c->PE;  // 8-byte scratch of n x chi (the energy runs in FP64)
       start_projector(c, n, Pref);
     }
   }
-  const void* PE = as_prec(c, Pref, e == DType::F64 ? nullptr : c->PE, (int64_t)n * chi);
-  if (e != DType::F64 && Pref == (double*)c->PE)
-    throw std::logic_error("projector scratch clash");
-  // 5. M = Ct P_prev (FP64 result)
+  if (e != DType::F64 && Pref != c->P) throw std::logic_error("projector scratch clash");
+  const void* PE = as_prec(c, e, Pref, c->PE, (int64_t)n * chi);
+  // 5. M = Ct P_prev (FP64 result), Q1 = thin QR factor
+  KernelEvents ev;
   gemm(s, e, n, chi, n, Operand{c->Ct, n, false}, Operand{PE, chi, false},
-       Output{c->M, chi, DType::F64}, 1, 1, 1.0, 0.0, c->ws);
+       Output{c->M, chi, DType::F64}, 1, 1, 1.0, 0.0, c->ws, 0, nullptr,
+       big_gemm_events(c, ev, n, chi, n));
   householder_qr(s, c->M, chi, n, chi, c->qr);
   householder_form_q(s, c->qr, n, chi, c->Q, chi);
-  launch_overlap_signs(s, Pref, c->Q, n, chi, c->part, c->sgn);
-  launch_apply_signs(s, c->Q, n, chi, c->sgn, update ? c->P : nullptr);
+  // basis: Q = Q1 gs(Q1^T P_prev)
+  gemm(s, DType::F64, chi, chi, n, Operand{c->Q, chi, true}, Operand{Pref, chi, false},
+       Output{c->Xs, chi, DType::F64}, 1, 1, 1.0, 0.0, c->ws);
+  gram_schmidt_small(c, c->Xs, chi, c->Xq);
+  gemm(s, DType::F64, n, chi, chi, Operand{c->Q, chi, false}, Operand{c->Xq, chi, false},
+       Output{c->M, chi, DType::F64}, 1, 1, 1.0, 0.0, c->ws);
+  std::swap(c->Q, c->M);
+  if (update)
+    CTM_HIP(hipMemcpyAsync(c->P, c->Q, (size_t)n * chi * sizeof(double), hipMemcpyDeviceToDevice, s));
 }
 
 void step_once(ctm_ctx* c) {
@@ -247,7 +313,11 @@ void step_once(ctm_ctx* c) {
   const DType e = c->prec;
   const int x = c->chi_c, D2 = c->D2, chi = c->chi;
   const int64_t n = (int64_t)x * D2;
+  c->prof_active = c->prof_on;
+  stage_begin(c, CTM_STAGE_CORNER);
   enlarged_corner(c, e);
+  stage_end(c, CTM_STAGE_CORNER);
+  stage_begin(c, CTM_STAGE_PROJECTOR);
   int xn;
   if (n <= chi) {
     xn = (int)n;
@@ -256,17 +326,24 @@ void step_once(ctm_ctx* c) {
     xn = chi;
     qr_projector(c, e, true);
   }
-  const void* QE = as_prec(c, c->Q, c->QE, n * xn);
+  stage_end(c, CTM_STAGE_PROJECTOR);
+  stage_begin(c, CTM_STAGE_RENORM_C);
+  const void* QE = as_prec(c, e, c->Q, c->QE, n * xn);
+  KernelEvents ev1, ev2, ev3;
   // 6. Gm = Ct Q
   gemm(s, e, (int)n, xn, (int)n, Operand{c->Ct, n, false}, Operand{QE, xn, false},
-       Output{c->Gm, xn, e}, 1, 1, 1.0, 0.0, c->ws);
+       Output{c->Gm, xn, e}, 1, 1, 1.0, 0.0, c->ws, 0, nullptr,
+       big_gemm_events(c, ev1, n, xn, n));
   // 7. C' = Q^T Gm, symmetrized and normalized
   gemm(s, e, xn, xn, (int)n, Operand{QE, xn, true}, Operand{c->Gm, xn, false},
        Output{c->Cp, xn, DType::F64}, 1, 1, 1.0, 0.0, c->ws);
   launch_corner_finalize(s, c->Cp, c->Cn, xn, c->flag);
+  stage_end(c, CTM_STAGE_RENORM_C);
+  stage_begin(c, CTM_STAGE_RENORM_T);
   // 8. V2 = V Q
   gemm(s, e, (int)n, xn, (int)n, Operand{c->V, n, false}, Operand{QE, xn, false},
-       Output{c->V2, xn, e}, 1, 1, 1.0, 0.0, c->ws);
+       Output{c->V2, xn, e}, 1, 1, 1.0, 0.0, c->ws, 0, nullptr,
+       big_gemm_events(c, ev2, n, xn, n));
   // 9. V3[alpha][(k,l)][nu] into the Ct buffer (Ct is no longer needed)
   const void* aE = e == DType::F64 ? (const void*)c->a : c->aE;
   void* V3 = c->Ct;
@@ -275,8 +352,11 @@ void step_once(ctm_ctx* c) {
   // 10. T' = Q^T V3, normalized
   const int64_t tn = (int64_t)xn * D2 * xn;
   gemm(s, e, xn, D2 * xn, (int)n, Operand{QE, xn, true}, Operand{V3, (int64_t)D2 * xn, false},
-       Output{c->Tp, (int64_t)D2 * xn, DType::F64}, 1, 1, 1.0, 0.0, c->ws, 0, c->sumsq);
+       Output{c->Tp, (int64_t)D2 * xn, DType::F64}, 1, 1, 1.0, 0.0, c->ws, 0, c->sumsq,
+       big_gemm_events(c, ev3, xn, (double)D2 * xn, n));
   launch_scale_by_norm(s, c->Tp, c->Tn, tn, c->sumsq, sumsq_blocks(xn, D2 * xn), c->flag);
+  stage_end(c, CTM_STAGE_RENORM_T);
+  c->prof_active = false;
   std::swap(c->C, c->Cn);
   std::swap(c->T, c->Tn);
   c->chi_c = xn;
@@ -426,9 +506,10 @@ void allocate(ctm_ctx* c) {
   c->M = c->allocd(nmax * chi);
   c->Q = c->allocd(nmax * chi);
   c->Cp = c->allocd(chi * chi);
+  c->Xs = c->allocd(chi * chi);
+  c->Xq = c->allocd(chi * chi);
   c->Tp = c->allocd(chi * D2 * chi);
   c->sgn = c->allocd(chi);
-  c->part = c->allocd((int64_t)overlap_blocks((int)nmax) * chi);
   c->sumsq = c->allocd(1024);
   c->dev_small = c->allocd(8);
   c->flag = (int*)c->alloc(sizeof(int) * 4);
@@ -640,6 +721,35 @@ int ctm_set_precision(ctm_ctx* c, int prec) {
     if (prec < CTM_PREC_FP64 || prec > CTM_PREC_BF16) throw std::invalid_argument("bad precision");
     c->prec = to_dtype(prec);
     c->cfg.prec = prec;
+    return CTM_OK;
+  });
+}
+
+int ctm_profile(ctm_ctx* c, int enable) {
+  return guarded(c, [&]() -> int {
+    CTM_HIP(hipStreamSynchronize(c->stream));
+    c->prof_on = enable != 0;
+    c->intervals.clear();
+    c->events_used = 0;
+    c->big_flops = 0.0;
+    return CTM_OK;
+  });
+}
+
+int ctm_profile_read(ctm_ctx* c, double* ms_host, int64_t* launches_host, double* flops_host) {
+  return guarded(c, [&]() -> int {
+    CTM_HIP(hipStreamSynchronize(c->stream));
+    double ms[CTM_NSTAGES] = {};
+    int64_t cnt[CTM_NSTAGES] = {};
+    for (const auto& iv : c->intervals) {
+      float t = 0.0f;
+      CTM_HIP(hipEventElapsedTime(&t, iv.begin, iv.end));
+      ms[iv.stage] += t;
+      cnt[iv.stage] += 1;
+    }
+    if (ms_host) std::memcpy(ms_host, ms, sizeof(ms));
+    if (launches_host) std::memcpy(launches_host, cnt, sizeof(cnt));
+    if (flops_host) *flops_host = c->big_flops;
     return CTM_OK;
   });
 }

@@ -319,7 +319,7 @@ size_t gemm_scratch_bytes(DType e, int M, int N) {
 
 void gemm(hipStream_t s, DType e, int M, int N, int K, const Operand& A, const Operand& B,
           const Output& C, int nb0, int nb1, double alpha, double beta, const Scratch& ws,
-          int ksplit, double* sumsq) {
+          int ksplit, double* sumsq, const KernelEvents* ev) {
   if (M <= 0 || N <= 0 || nb0 <= 0 || nb1 <= 0) return;
   const int cfg = pick_cfg(M, N);
   const int BM = CFGS[cfg].BM, BN = CFGS[cfg].BN;
@@ -371,12 +371,14 @@ void gemm(hipStream_t s, DType e, int M, int N, int K, const Operand& A, const O
     a.C = ws.p;
   }
   dim3 grid((unsigned)(tiles * nbatch), split ? ksplit : 1);
+  if (ev) CTM_HIP(hipEventRecord(ev->begin, s));
   switch (e) {
     case DType::F64: launch_any<double>(split, A.trans, B.trans, cfg, grid, s, a); break;
     case DType::F32: launch_any<float>(split, A.trans, B.trans, cfg, grid, s, a); break;
     case DType::BF16: launch_any<bf16>(split, A.trans, B.trans, cfg, grid, s, a); break;
   }
   CTM_LAUNCHED();
+  if (ev) CTM_HIP(hipEventRecord(ev->end, s));
   if (split) {
     if (acc_t == DType::F64)
       launch_reduce<double>(C.t, (const double*)ws.p, ksplit, M, N, C.p, C.ld, alpha, beta, sumsq, s);

@@ -40,9 +40,15 @@ struct Scratch {
 // If sumsq is non-null (unbatched products only) the reduction also writes
 // per-block partial sums of squares of the final C there (see
 // sumsq_blocks()).
+// Optional HIP events recorded right before and after the product kernel
+// (not the split-K reduction).
+struct KernelEvents {
+  hipEvent_t begin = nullptr, end = nullptr;
+};
+
 void gemm(hipStream_t s, DType e, int M, int N, int K, const Operand& A, const Operand& B,
           const Output& C, int nb0, int nb1, double alpha, double beta, const Scratch& ws,
-          int ksplit = 0, double* sumsq = nullptr);
+          int ksplit = 0, double* sumsq = nullptr, const KernelEvents* ev = nullptr);
 
 // Number of partial sums written to `sumsq` by gemm() for an M x N output.
 int sumsq_blocks(int M, int N);

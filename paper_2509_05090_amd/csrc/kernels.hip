@@ -148,26 +148,6 @@ __global__ void diag_signs_kernel(const double* M, int ld, int k, double* sgn) {
     sgn[j] = M[(size_t)j * ld + j] < 0.0 ? -1.0 : 1.0;
 }
 
-constexpr int OVL_ROWS = 64;
-
-__global__ void overlap_partial_kernel(const double* P, const double* Q, int n, int k,
-                                       double* part) {
-  const int r0 = blockIdx.x * OVL_ROWS, r1 = min(n, r0 + OVL_ROWS);
-  for (int j = threadIdx.x; j < k; j += blockDim.x) {
-    double t = 0.0;
-    for (int r = r0; r < r1; ++r) t += P[(size_t)r * k + j] * Q[(size_t)r * k + j];
-    part[(size_t)blockIdx.x * k + j] = t;
-  }
-}
-
-__global__ void overlap_final_kernel(const double* part, int nb, int k, double* sgn) {
-  for (int j = threadIdx.x; j < k; j += blockDim.x) {
-    double t = 0.0;
-    for (int b = 0; b < nb; ++b) t += part[(size_t)b * k + j];
-    sgn[j] = t < 0.0 ? -1.0 : 1.0;
-  }
-}
-
 __global__ void apply_signs_kernel(double* Q, int n, int k, const double* sgn, double* copy) {
   const int64_t total = (int64_t)n * k;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
@@ -309,17 +289,6 @@ void launch_eye(hipStream_t s, void* Q, DType t, int n, int k, int64_t ld) {
 
 void launch_diag_signs(hipStream_t s, const double* M, int ld, int k, double* sgn) {
   diag_signs_kernel<<<1, 256, 0, s>>>(M, ld, k, sgn);
-  CTM_LAUNCHED();
-}
-
-int overlap_blocks(int n) { return (int)cdiv(n, OVL_ROWS); }
-
-void launch_overlap_signs(hipStream_t s, const double* P, const double* Q, int n, int k,
-                          double* part, double* sgn) {
-  const int nb = overlap_blocks(n);
-  overlap_partial_kernel<<<nb, 256, 0, s>>>(P, Q, n, k, part);
-  CTM_LAUNCHED();
-  overlap_final_kernel<<<1, 256, 0, s>>>(part, nb, k, sgn);
   CTM_LAUNCHED();
 }
 

@@ -24,11 +24,6 @@ void launch_cast(hipStream_t s, const double* src, void* dst, DType t, int64_t n
 void launch_eye(hipStream_t s, void* Q, DType t, int n, int k, int64_t ld);
 // sgn[j] = -1 if M[j][j] < 0 else +1.
 void launch_diag_signs(hipStream_t s, const double* M, int ld, int k, double* sgn);
-// sgn[j] = sign(sum_r P[r][j] Q[r][j]) (zero counts as +1); part: scratch of
-// overlap_blocks(n) * k doubles.
-int overlap_blocks(int n);
-void launch_overlap_signs(hipStream_t s, const double* P, const double* Q, int n, int k,
-                          double* part, double* sgn);
 // Q[:, j] *= sgn[j]; copy (nullable) = Q afterwards.
 void launch_apply_signs(hipStream_t s, double* Q, int n, int k, const double* sgn, double* copy);
 // Cout = sym(Cin) / ||sym(Cin)||_F (k x k); flag |= 1 if the norm is 0 or not finite.

@@ -32,7 +32,9 @@ DTYPE_CODE = {"float64": 0, "float32": 1, "bfloat16": 2}
 
 EXPORTS = ("ctm_symmetrize", "ctm_init", "ctm_step", "ctm_converge", "ctm_energy",
            "ctm_spectrum", "ctm_query", "ctm_get_env", "ctm_set_env", "ctm_set_precision",
-           "ctm_free", "ctm_last_error", "ctm_gemm", "ctm_qr")
+           "ctm_free", "ctm_last_error", "ctm_gemm", "ctm_qr", "ctm_profile",
+           "ctm_profile_read")
+STAGES = ("corner", "projector", "renorm_c", "renorm_t", "big_gemm")
 
 
 class CtmError(RuntimeError):
@@ -68,6 +70,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "ctm_gemm": (i, [i, i, i, i, vp, i64, i, i64, i64, vp, i64, i, i64, i64,
                          vp, i64, i, i64, i64, i, i, d, d, i, vp]),
         "ctm_qr": (i, [vp, i, i, vp, vp, vp]),
+        "ctm_profile": (i, [vp, i]),
+        "ctm_profile_read": (i, [vp, pd, ctypes.POINTER(i64), pd]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -212,6 +216,17 @@ class Context:
         pr = 0 if P is None else P.shape[0]
         _check(_lib.ctm_set_env(self._h, x, _ptr(C.contiguous()), _ptr(T.contiguous()), pr,
                                 _ptr(None if P is None else P.contiguous())), self._h)
+
+    def profile(self, enable: bool = True):
+        _check(_lib.ctm_profile(self._h, int(enable)), self._h)
+
+    def profile_read(self):
+        """{stage: (ms, intervals)} and the big-product flop count."""
+        ms = (ctypes.c_double * len(STAGES))()
+        cnt = (ctypes.c_int64 * len(STAGES))()
+        fl = ctypes.c_double(0.0)
+        _check(_lib.ctm_profile_read(self._h, ms, cnt, ctypes.byref(fl)), self._h)
+        return {name: (ms[i], cnt[i]) for i, name in enumerate(STAGES)}, fl.value
 
     def set_precision(self, prec: str):
         _check(_lib.ctm_set_precision(self._h, PREC[prec]), self._h)

@@ -25,7 +25,8 @@ import numpy as np  # noqa: E402
 import ctm_inputs as ci  # noqa: E402
 from oracle import ctm  # noqa: E402
 
-MAX_STEPS = {"c1": 50, "c2": 3000, "c3": 1500, "c4": 3000}
+MAX_STEPS = {"c1": 50, "c2": 3000, "c3": 1200, "c4": 3000}
+CHECKPOINTS = (10, 20, 50, 100, 200, 400)
 PROJECTORS = {"c1": ("qr",), "c2": ("qr", "evd"), "c3": ("qr",), "c4": ("qr",)}
 
 
@@ -34,20 +35,21 @@ def run(key: str, proj: str) -> dict:
     A = ctm.prepare_site_tensor(ci.raw_site_tensor(w))
     G = ci.start_matrix(w)
     st = ctm.State(A, w.chi, G, proj=proj)
+    ops = ci.bond_operators(w)
+    h_site = ci.site_energy_operator(w)
     t0 = time.time()
     history = []
-    if w.steps is not None:
-        for _ in range(w.steps):
-            history.append(st.step())
-    else:
-        for _ in range(MAX_STEPS[key]):
-            history.append(st.step())
-            if history[-1] < w.tol:
-                break
+    at_steps = {}
+    limit = w.steps if w.steps is not None else MAX_STEPS[key]
+    for k in range(1, limit + 1):
+        history.append(st.step())
+        if k in CHECKPOINTS:
+            at_steps[k] = st.energy(h_site)
+        if w.steps is None and history[-1] < w.tol:
+            break
     elapsed = time.time() - t0
     env = st.measurement_environment()
     rho = ctm.bond_density_matrix(st.C, st.T, st.A, env)
-    ops = ci.bond_operators(w)
     e = {k: ctm.expectation(rho, v) for k, v in ops.items()}
     return {
         "workload": key,
@@ -61,9 +63,11 @@ def run(key: str, proj: str) -> dict:
         "tol": w.tol,
         "e_bond": e,
         "e_site": 0.5 * sum(e.values()),
+        "e_site_at_step": at_steps,
         "rho": rho.tolist(),
         "spectrum": st.spectrum.tolist(),
         "oracle_seconds": elapsed,
+        "gauge": st.gauge if proj == "qr" else None,
     }
 
 

@@ -178,10 +178,10 @@ def test_brute_force_catches_wrong_corner(monkeypatch):
 
 
 # ------------------------------------------------------------------ P4, P5
-def truncated_state(D=2, chi=8, steps=30, proj="qr", seed=7, rr=False):
+def truncated_state(D=2, chi=8, steps=30, proj="qr", seed=7, rr=False, gauge="align"):
     A = rand_sym(2, D, seed)
     G = ci.gaussian((chi * D * D, chi), 99)
-    st = ctm.State(A, chi, G, proj=proj, rr_gauge=rr)
+    st = ctm.State(A, chi, G, proj=proj, rr_gauge=rr, gauge="sign" if rr else gauge)
     st.run(steps=steps)
     return st
 
@@ -249,6 +249,50 @@ def test_rayleigh_ritz_gives_elementwise_fixed_point():
     lhs = Ct @ Q
     C = Q.T @ Ct @ Q
     assert np.linalg.norm(lhs - Q @ C) / np.linalg.norm(Ct) < 1e-10
+
+
+def test_sign_gauge_two_cycle_on_plus_minus_pair():
+    """Why the basis must be tied to P_prev: for an exact +-lambda pair one
+    QR sweep flips the off-diagonal of the 2x2 block, a two-cycle that column
+    signs cannot remove; the aligned basis is stationary."""
+    a, b = 0.6, 0.8
+    Ct = np.array([[a, b], [b, -a]])          # eigenvalues +-1
+    P = np.eye(2)
+    Q, _ = np.linalg.qr(Ct @ P)
+    C1 = ctm.align_signs(Q, P).T @ Ct @ ctm.align_signs(Q, P)
+    assert abs(C1[0, 1] + b) < 1e-15          # off-diagonal flipped
+    Qa = ctm.align_basis(Q, P)
+    assert np.abs(Qa - P).max() < 1e-15       # aligned basis: no change
+
+
+def test_align_basis_properties():
+    r = np.random.default_rng(3)
+    Q, _ = np.linalg.qr(r.standard_normal((30, 6)))
+    P, _ = np.linalg.qr(r.standard_normal((30, 6)))
+    Qa = ctm.align_basis(Q, P)
+    assert np.abs(Qa.T @ Qa - np.eye(6)).max() < 1e-14          # isometry
+    assert np.abs(Qa @ Qa.T - Q @ Q.T).max() < 1e-14            # same span
+    O = Qa.T @ P
+    assert np.abs(np.tril(O, -1)).max() < 1e-14 and (np.diag(O) > 0).all()
+    U, _ = np.linalg.qr(r.standard_normal((6, 6)))
+    assert np.abs(ctm.align_basis(P @ U, P) - P).max() < 1e-14  # fixed point
+
+
+def test_plus_minus_pairs_converge_to_evd_fixed_point():
+    """Seed 1002 at D=4 gives an enlarged corner whose spectrum pairs as
+    +-lambda; the aligned QR projector must still reach the energy of the
+    eigendecomposition projector (chi=16)."""
+    A = ctm.prepare_site_tensor(ci.gaussian((2, 4, 4, 4), 1002))
+    G = ci.gaussian((16 * 16, 16), 1009)
+    e = {}
+    for proj in ("qr", "evd"):
+        st = ctm.State(A, 16, G, proj=proj)
+        st.run(steps=400 if proj == "qr" else 60)
+        e[proj] = st.energy(H_ROT)
+    lam = np.linalg.eigvalsh(ctm.enlarged_corner(st.C, st.T, st.a))
+    lam = lam[ctm.order_by_magnitude(lam)]
+    assert abs(abs(lam[0]) - abs(lam[1])) < 1e-10 * abs(lam[0]) and lam[0] * lam[1] < 0
+    assert abs(e["qr"] - e["evd"]) < 1e-10
 
 
 def test_subspace_residual_small_without_rr():

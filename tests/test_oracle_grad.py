@@ -51,7 +51,7 @@ def test_tracked_steps_converge(setup):
     A, chi, G, st, E, g = setup
     _, g10 = grad.gradient(A, st.C, st.T, st.P, chi, 10, H_SITE)
     _, g80 = grad.gradient(A, st.C, st.T, st.P, chi, 80, H_SITE)
-    assert np.abs(g80 - g).max() <= np.abs(g10 - g).max() + 1e-15
+    assert np.abs(g80 - g).max() <= np.abs(g10 - g).max() + 1e-13
     assert np.abs(g80 - g).max() < 1e-10
 
 
