@@ -485,7 +485,7 @@ bool valid_cfg(const ctm_config* cfg, std::string& why) {
   if (!cfg) return why = "null config", false;
   if (cfg->d < 1 || cfg->D < 1 || cfg->chi < 1) return why = "d, D and chi must be >= 1", false;
   if ((int64_t)cfg->d * cfg->D * cfg->D * cfg->D > 16384) return why = "d*D^3 > 16384", false;
-  if ((int64_t)cfg->chi * cfg->D * cfg->D > (1 << 20)) return why = "chi*D^2 too large", false;
+  if ((int64_t)cfg->chi * cfg->D * cfg->D > QR_MAX_ROWS) return why = "chi*D^2 > 32768", false;
   if (cfg->proj != CTM_PROJ_QR)
     return why = "only the QR projector (CTM_PROJ_QR) is implemented", false;
   if (cfg->prec < CTM_PREC_FP64 || cfg->prec > CTM_PREC_BF16) return why = "bad precision", false;
@@ -524,13 +524,8 @@ void allocate(ctm_ctx* c) {
   c->Ct = c->allocd(nmax * nmax);
   c->Gm = c->allocd(nmax * chi);
   c->V2 = c->allocd(nmax * chi);
-  c->qr.Y = c->allocd(nmax * chi);
-  c->qr.tau = c->allocd(chi);
-  c->qr.Tf = c->allocd(cdiv(chi, QR_NB) * QR_NB * QR_NB);
-  c->qr.W = c->allocd((int64_t)QR_NB * chi);
-  c->qr.W2 = c->allocd((int64_t)QR_NB * chi);
-  c->qr.ws.bytes = gemm_scratch_bytes(DType::F64, QR_NB, (int)chi);
-  c->qr.ws.p = c->alloc(c->qr.ws.bytes);
+  c->qr = qr_work_carve(c->stream, c->alloc(qr_work_bytes((int)nmax, (int)chi)), (int)nmax,
+                        (int)chi);
   size_t wsb = std::max(gemm_scratch_bytes(DType::F64, (int)nmax, (int)chi),
                         gemm_scratch_bytes(DType::F64, (int)chi, (int)chi));
   c->ws.bytes = wsb;

@@ -65,22 +65,14 @@ extern "C" int ctm_gemm(int prec, int M, int N, int K, const void* A, int64_t ld
 
 extern "C" int ctm_qr(const double* M_dev, int n, int k, double* Q_dev, double* R_dev,
                       void* stream) {
-  if (!M_dev || !Q_dev || k < 1 || n < k) {
+  if (!M_dev || !Q_dev || k < 1 || n < k || n > QR_MAX_ROWS) {
     set_global_error("ctm_qr: bad arguments");
     return CTM_EINVAL;
   }
   try {
     hipStream_t s = (hipStream_t)stream;
-    DevBuf Mw((size_t)n * k * 8), Y((size_t)n * k * 8), tau((size_t)k * 8),
-        Tf((size_t)cdiv(k, QR_NB) * QR_NB * QR_NB * 8), W((size_t)QR_NB * k * 8),
-        W2((size_t)QR_NB * k * 8), ws(gemm_scratch_bytes(DType::F64, QR_NB, k));
-    QrWork w;
-    w.Y = (double*)Y.p;
-    w.tau = (double*)tau.p;
-    w.Tf = (double*)Tf.p;
-    w.W = (double*)W.p;
-    w.W2 = (double*)W2.p;
-    w.ws = Scratch{ws.p, gemm_scratch_bytes(DType::F64, QR_NB, k)};
+    DevBuf Mw((size_t)n * k * 8), ws(qr_work_bytes(n, k));
+    QrWork w = qr_work_carve(s, ws.p, n, k);
     CTM_HIP(hipMemcpyAsync(Mw.p, M_dev, (size_t)n * k * 8, hipMemcpyDeviceToDevice, s));
     householder_qr(s, (double*)Mw.p, k, n, k, w);
     householder_form_q(s, w, n, k, Q_dev, k);

@@ -90,8 +90,14 @@ def test_gemm_two_level_batch(prec):
     assert err.max() < max(TOL[prec], TOL_OUT[prec]), err.max()
 
 
-@pytest.mark.parametrize("n,k", [(16, 16), (40, 16), (200, 37), (1024, 64), (1600, 100), (5184, 144)])
+QR_SHAPES = [(16, 16), (40, 16), (200, 37), (1024, 64), (1600, 100), (5184, 144), (144, 144),
+             (513, 33), (1025, 64), (9000, 100), (16384, 256), (30000, 40), (7, 1)]
+
+
+@pytest.mark.parametrize("n,k", QR_SHAPES)
 def test_householder_qr(n, k):
+    """Shapes with one leaf, several leaves (ragged last leaf), two rows per
+    thread in the leaves (n > 8192) and in the stacked factorization."""
     M = _rng(n + k).standard_normal((n, k))
     Q, R = ctm.qr(torch.tensor(M, device=DEV))
     torch.cuda.synchronize()
@@ -114,3 +120,31 @@ def test_householder_qr_rank_deficient():
     Q, R = Q.cpu().numpy(), R.cpu().numpy()
     assert np.abs(Q.T @ Q - np.eye(20)).max() < 1e-13
     assert np.abs(Q @ R - M).max() < 1e-12 * np.abs(M).max()
+
+
+def test_householder_qr_ill_conditioned():
+    """Columns scaled over 12 decades (the reduced corner's spread): Q must
+    stay orthonormal and span the same space as LAPACK's Q column by column
+    (the leading j columns of both span the same space)."""
+    r = _rng(9)
+    n, k = 5184, 144
+    M = r.standard_normal((n, k)) * np.logspace(0, -12, k)[None, :]
+    Q, R = ctm.qr(torch.tensor(M, device=DEV))
+    Q, R = Q.cpu().numpy(), R.cpu().numpy()
+    assert np.abs(Q.T @ Q - np.eye(k)).max() < 1e-13
+    assert np.abs(Q @ R - M).max() < 1e-13 * np.abs(M).max() * np.sqrt(n)
+    Ql, _ = np.linalg.qr(M)
+    # column j of Q equals +-column j of LAPACK's Q up to the conditioning of
+    # the leading j columns; compare the projectors on the first 20 columns
+    P1, P2 = Q[:, :20] @ Q[:, :20].T, Ql[:, :20] @ Ql[:, :20].T
+    assert np.abs(P1 - P2).max() < 1e-9
+
+
+def test_householder_qr_repeated_calls_are_identical():
+    """The stacked factorization is done by whichever leaf finishes last;
+    results must not depend on that order."""
+    M = torch.tensor(_rng(77).standard_normal((5184, 144)), device=DEV)
+    Q1, R1 = ctm.qr(M)
+    for _ in range(3):
+        Q2, R2 = ctm.qr(M)
+        assert torch.equal(Q1, Q2) and torch.equal(R1, R2)
