@@ -1,103 +1,185 @@
 // Blocked Householder QR (FP64) for tall-skinny matrices, with each panel
 // factored as a tall-skinny QR (TSQR) over row blocks.
 //
-// Panel kernel: one workgroup of 512 threads per leaf (row block of up to
-// 512 or 1024 rows) holds its block of the panel in registers, one or two
-// rows per thread, and factors it column by column.  Per column a single
-// reduction gives, for the rows below the pivot, the column's squared norm,
-// its inner products with the later panel columns and with the earlier
-// Householder vectors (the latter build the compact WY factor T).  The
-// reduction is a reduce-scatter across the 64 lanes of a wavefront (the
-// 32 partial sums are halved at each exchange, 32 exchanges instead of
-// 32 x 6), then one LDS pass across the 8 wavefronts.  The reflector
-// follows LAPACK's dlarfg (beta = -sign(x0) ||x||).  Leaves write their
+// Panel kernel: one workgroup of 256 threads (one wavefront per SIMD) per
+// leaf holds its row block of the panel in registers, RPT rows per thread,
+// and runs the Householder column loop.  The register window rotates: the
+// columns are processed four at a time at fixed register positions 0..3, and
+// after each group the finished columns (reflectors below the diagonal, R on
+// and above it) are written out and the window shifts by four.  Per column a
+// single reduction gives, for the rows below the pivot, the column's squared
+// norm and its inner products with the later columns; it is a
+// reduce-scatter across the 64 lanes of a wavefront (permlane swaps across
+// the 32- and 16-lane halves, DPP within rows of 16), then one LDS pass
+// across the four wavefronts.  The reflector follows LAPACK's dlarfg
+// (beta = -sign(x0) ||x||); an already-zero column gets the reflector
+// I - 2 e e^T, which keeps every reflector's tau in [1, 2].  The compact WY
+// factor comes from the Gram matrix of the reflectors (Joffrain, Low,
+// Quintana-Orti, van de Geijn, van Zee, ACM TOMS 32 (2006)):
+// T^{-1} = diag(1/tau) + strictly-upper(Y^T Y), the Gram matrix on the
+// matrix cores, the triangular inverse by one wavefront.  Leaves write their
 // triangular factors to a stack; the last leaf to finish (atomic counter,
 // no waiting) factors the stack in the same way.
 //
 // Apply kernel: B <- (I - Y op(T) Y^T) B on a range of columns, per leaf
-// (row block) or on the stacked rows, 32 columns per workgroup: W = Y^T B,
-// W <- op(T) W, B <- B - Y W, with LDS-staged 64-row tiles.
+// (row block) or on the stacked rows, 16 columns and 16 wavefronts per
+// workgroup: W = Y^T B, W <- op(T) W, B <- B - Y W on the FP64 matrix cores.
 #include "qr.hpp"
 
 namespace ctm {
 
 namespace {
 
-constexpr int NB = QR_NB;
-constexpr int QT = 512;  // threads of the panel workgroups
-constexpr int NW = QT / 64;
+constexpr int QT = 256;  // threads of the panel workgroups
+constexpr int QW = QT / 64;
 
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+template <int NBT>
 struct QrShared {
-  double red[2][NW][NB];
-  double fin[2][NB];
-  double prow[2][NB];
-  double T[NB][NB + 1];
+  double red[2][QW][NBT];   // per-wavefront partial sums per window position
+  double piv[2][NBT];       // pivot row
+  double tau[NBT];
+  double G[NBT][NBT + 1];   // Gram matrix of the reflectors
+  double Gp[QW][NBT][NBT + 1];
   int last;
 };
 
-// Lane l ends the reduce-scatter holding the wavefront sum of this index.
-__device__ inline int rs_index(int lane) {
-  return ((lane >> 5) & 1) * 16 + ((lane >> 4) & 1) * 8 + ((lane >> 3) & 1) * 4 +
-         ((lane >> 2) & 1) * 2 + ((lane >> 1) & 1);
+__device__ __forceinline__ unsigned lo32(double v) {
+  return (unsigned)__builtin_bit_cast(unsigned long long, v);
+}
+__device__ __forceinline__ unsigned hi32(double v) {
+  return (unsigned)(__builtin_bit_cast(unsigned long long, v) >> 32);
+}
+__device__ __forceinline__ double mk64(unsigned lo, unsigned hi) {
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
-template <int N>
-__device__ __forceinline__ void rs_halve(const double (&in)[2 * N], double (&out)[N], bool up, int off) {
+// Exchange across the two halves of the wavefront (lanes l and l^32) or of
+// each 32-lane half (l and l^16): with x the value of the lower index half
+// and y that of the upper, the permlane swaps leave in every lane its own
+// kept value plus its partner's copy of it, so the sum is the pair sum of
+// the half the lane keeps (lower half if the lane's bit is 0).
+__device__ __forceinline__ double pair_sum32(double x, double y) {
+  const auto l = __builtin_amdgcn_permlane32_swap(lo32(x), lo32(y), false, false);
+  const auto h = __builtin_amdgcn_permlane32_swap(hi32(x), hi32(y), false, false);
+  return mk64(l[0], h[0]) + mk64(l[1], h[1]);
+}
+__device__ __forceinline__ double pair_sum16(double x, double y) {
+  const auto l = __builtin_amdgcn_permlane16_swap(lo32(x), lo32(y), false, false);
+  const auto h = __builtin_amdgcn_permlane16_swap(hi32(x), hi32(y), false, false);
+  return mk64(l[0], h[0]) + mk64(l[1], h[1]);
+}
+
+// Value of the partner lane within a row of 16 lanes through DPP: row_ror:8
+// (partner l^8), row_half_mirror (partner 7-l within 8: differs in bit 2),
+// quad_perm [2,3,0,1] (l^2) and [1,0,3,2] (l^1).
+template <int CTRL>
+__device__ __forceinline__ double dpp64(double v) {
+  const int l = __builtin_amdgcn_update_dpp(0, (int)lo32(v), CTRL, 0xF, 0xF, false);
+  const int h = __builtin_amdgcn_update_dpp(0, (int)hi32(v), CTRL, 0xF, 0xF, false);
+  return mk64((unsigned)l, (unsigned)h);
+}
+
+// Value of lane k (uniform) of v, in every lane.
+__device__ __forceinline__ double bcast64(double v, int k) {
+  return mk64((unsigned)__builtin_amdgcn_readlane((int)lo32(v), k),
+              (unsigned)__builtin_amdgcn_readlane((int)hi32(v), k));
+}
+
+template <int N, int CTRL>
+__device__ __forceinline__ void rs_halve(const double (&in)[2 * N], double (&out)[N], bool up) {
 #pragma unroll
   for (int j = 0; j < N; ++j) {
     const double keep = up ? in[j + N] : in[j], send = up ? in[j] : in[j + N];
-    out[j] = keep + __shfl_xor(send, off);
+    out[j] = keep + dpp64<CTRL>(send);
   }
 }
 
-// Column c of a local Householder QR of the rows held by this workgroup
-// (row t = tid + r * QT in a[r][*]); w = columns in use.
-template <int RPT, int c>
-__device__ __forceinline__ void qr_column(double (&a)[RPT][NB], int w, QrShared& sh, int tid) {
+// Reduce-scatter of NBT per-lane values f[0..NBT) over the wavefront.  On
+// return every lane holds the wavefront sum of index rs_index<NBT>(lane).
+template <int NBT>
+__device__ __forceinline__ int rs_index(int lane) {
+  if constexpr (NBT == 32)
+    return ((lane >> 5) & 1) * 16 + ((lane >> 4) & 1) * 8 + ((lane >> 3) & 1) * 4 +
+           ((lane >> 2) & 1) * 2 + ((lane >> 1) & 1);
+  else
+    return ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 + ((lane >> 3) & 1) * 2 +
+           ((lane >> 2) & 1);
+}
+// Lanes holding a distinct index (the others hold copies).
+template <int NBT>
+__device__ __forceinline__ bool rs_writer(int lane) {
+  return NBT == 32 ? (lane & 1) == 0 : (lane & 3) == 0;
+}
+
+// Column at window position P (absolute column c) of the local Householder
+// QR; rows t = tid + r * QT held in a[r][*].
+template <int NBT, int RPT, int P>
+__device__ __forceinline__ void qr_column(double (&a)[RPT][NBT], int c, QrShared<NBT>& sh,
+                                          int tid) {
   const int lane = tid & 63, wid = tid >> 6;
-  constexpr int buf = c & 1;
+  const int buf = c & 1;
   double x[RPT];
 #pragma unroll
-  for (int r = 0; r < RPT; ++r) x[r] = tid + r * QT > c ? a[r][c] : 0.0;
-  double h16[16];
-  {
-    const bool up = lane & 32;
+  for (int r = 0; r < RPT; ++r) x[r] = tid + r * QT > c ? a[r][P] : 0.0;
+  double hsum;
+  if constexpr (NBT == 32) {
+    double h16[16], h8[8], h4[4], h2[2], h1[1];
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
       double lo = 0.0, hi = 0.0;
 #pragma unroll
       for (int r = 0; r < RPT; ++r) {
-        lo += x[r] * a[r][j];
+        if (j >= P) lo += x[r] * a[r][j];
         hi += x[r] * a[r][j + 16];
       }
-      const double keep = up ? hi : lo, send = up ? lo : hi;
-      h16[j] = keep + __shfl_xor(send, 32);
+      h16[j] = pair_sum32(lo, hi);
     }
-  }
-  double h8[8], h4[4], h2[2], h1[1];
-  rs_halve<8>(h16, h8, lane & 16, 16);
-  rs_halve<4>(h8, h4, lane & 8, 8);
-  rs_halve<2>(h4, h2, lane & 4, 4);
-  rs_halve<1>(h2, h1, lane & 2, 2);
-  const double hsum = h1[0] + __shfl_xor(h1[0], 1);
-  if ((lane & 1) == 0) sh.red[buf][wid][rs_index(lane)] = hsum;
-  if (tid == c) {
 #pragma unroll
-    for (int q = 0; q < NB; ++q) sh.prow[buf][q] = a[0][q];
+    for (int j = 0; j < 8; ++j) h8[j] = pair_sum16(h16[j], h16[j + 8]);
+    rs_halve<4, 0x128>(h8, h4, lane & 8);
+    rs_halve<2, 0x141>(h4, h2, lane & 4);
+    rs_halve<1, 0x4E>(h2, h1, lane & 2);
+    hsum = h1[0] + dpp64<0xB1>(h1[0]);
+  } else {
+    double h8[8], h4[4], h2[2], h1[1];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      double lo = 0.0, hi = 0.0;
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) {
+        if (j >= P) lo += x[r] * a[r][j];
+        hi += x[r] * a[r][j + 8];
+      }
+      h8[j] = pair_sum32(lo, hi);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) h4[j] = pair_sum16(h8[j], h8[j + 4]);
+    rs_halve<2, 0x128>(h4, h2, lane & 8);
+    rs_halve<1, 0x141>(h2, h1, lane & 4);
+    hsum = h1[0] + dpp64<0x4E>(h1[0]);
+    hsum = hsum + dpp64<0xB1>(hsum);
+  }
+  if (rs_writer<NBT>(lane)) sh.red[buf][wid][rs_index<NBT>(lane)] = hsum;
+  const bool pivot = tid == c;
+  if (pivot) {
+#pragma unroll
+    for (int q = 0; q < NBT; ++q) sh.piv[buf][q] = a[0][q];
   }
   __syncthreads();
-  if (tid < NB) {
-    double s = 0.0;
+  // Every wavefront forms the full sums itself: lane k < NBT holds the sum and
+  // the pivot row value of window position k; the rest is read by broadcast.
+  const int kl = lane & (NBT - 1);
+  double f = 0.0;
 #pragma unroll
-    for (int v = 0; v < NW; ++v) s += sh.red[buf][v][tid];
-    sh.fin[buf][tid] = s;
-  }
-  __syncthreads();
-  const double x0 = sh.prow[buf][c], sigma = sh.fin[buf][c];
+  for (int v = 0; v < QW; ++v) f += sh.red[buf][v][kl];
+  const double pk = sh.piv[buf][kl];
+  const double x0 = bcast64(pk, P), sigma = bcast64(f, P);
   double beta, tau, scale;
   if (sigma == 0.0) {
-    tau = 0.0;
-    beta = x0;
+    tau = 2.0;
+    beta = -x0;
     scale = 0.0;
   } else {
     const double nrm = sqrt(x0 * x0 + sigma);
@@ -105,107 +187,153 @@ __device__ __forceinline__ void qr_column(double (&a)[RPT][NB], int w, QrShared&
     tau = (beta - x0) / beta;
     scale = 1.0 / (x0 - beta);
   }
-  // column c of T: T[i][c] = -tau sum_{i2 = i..c-1} T[i][i2] (y_i2 . v_c),
-  // y_i2 . v_c = Y[c][i2] + scale * (sum over rows below c of Y[.][i2] x)
-  if (tid < c) {
-    double t = 0.0;
-    for (int i2 = tid; i2 < c; ++i2)
-      t += sh.T[tid][i2] * (sh.prow[buf][i2] + scale * sh.fin[buf][i2]);
-    sh.T[tid][c] = -tau * t;
-  }
-  if (tid == c) sh.T[c][c] = tau;
-  double v[RPT];
+  if (tid == 0) sh.tau[c & (NBT - 1)] = tau;
+  const double wlane = pk + scale * f;  // v^T a_k for k = lane
+  // reflector entries of this thread's rows: x scale below the pivot, 1 on
+  // it, 0 above
+  double tv[RPT], v[RPT];
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
-    const bool below = tid + r * QT > c;
-    v[r] = below ? a[r][c] * scale : 0.0;
-    if (below) a[r][c] = v[r];
+    v[r] = x[r] * scale;
+    if (r == 0 && pivot) v[r] = 1.0;
+    tv[r] = tau * v[r];
   }
+  // later columns: a_k -= tau v (v^T a_k)
 #pragma unroll
-  for (int k = c + 1; k < NB; ++k) {
-    if (k < w) {
-      const double wk = sh.prow[buf][k] + scale * sh.fin[buf][k];
+  for (int k = P + 1; k < NBT; ++k) {
+    const double wk = bcast64(wlane, k);
 #pragma unroll
-      for (int r = 0; r < RPT; ++r) a[r][k] -= tau * v[r] * wk;
-      if (tid == c) a[0][k] = sh.prow[buf][k] - tau * wk;
-    }
+    for (int r = 0; r < RPT; ++r) a[r][k] -= tv[r] * wk;
   }
-  if (tid == c) a[0][c] = beta;
+  // column c: the reflector below the pivot, beta on it
+#pragma unroll
+  for (int r = 0; r < RPT; ++r)
+    if (tid + r * QT > c) a[r][P] = v[r];
+  if (pivot) a[0][P] = beta;
 }
 
-template <int RPT, int c>
-struct QrCols {
-  __device__ static __forceinline__ void run(double (&a)[RPT][NB], int w, QrShared& sh, int tid) {
-    if (c < w) {
-      qr_column<RPT, c>(a, w, sh, tid);
-      QrCols<RPT, c + 1>::run(a, w, sh, tid);
+// Local Householder QR of m rows x w columns held in registers.  Writes the
+// reflectors to Y (m x w, unit diagonal, zeros above; leading dimension
+// ldy), R to Rd (w x w upper triangle, zeros below; leading dimension ldr)
+// and the compact WY factor to Tout (NBT x NBT, zero outside w x w).
+template <int NBT, int RPT>
+__device__ __forceinline__ void local_qr(double (&a)[RPT][NBT], int m, int w, QrShared<NBT>& sh,
+                                         int tid, double* __restrict__ Y, int64_t ldy,
+                                         double* __restrict__ Rd, int64_t ldr,
+                                         double* __restrict__ Tout) {
+#pragma unroll 1
+  for (int c0 = 0; c0 < w; c0 += 4) {
+    qr_column<NBT, RPT, 0>(a, c0, sh, tid);
+    if (c0 + 1 < w) qr_column<NBT, RPT, 1>(a, c0 + 1, sh, tid);
+    if (c0 + 2 < w) qr_column<NBT, RPT, 2>(a, c0 + 2, sh, tid);
+    if (c0 + 3 < w) qr_column<NBT, RPT, 3>(a, c0 + 3, sh, tid);
+    // write out the four finished columns, then shift the window
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const int t = tid + r * QT;
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const int c = c0 + p;
+        if (c < w && t < m) {
+          Y[(int64_t)t * ldy + c] = t > c ? a[r][p] : (t == c ? 1.0 : 0.0);
+          if (t < w) Rd[(int64_t)t * ldr + c] = t <= c ? a[r][p] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q + 4 < NBT; ++q) a[r][q] = a[r][q + 4];
+#pragma unroll
+      for (int q = NBT - 4; q < NBT; ++q) a[r][q] = 0.0;
     }
   }
-};
-template <int RPT>
-struct QrCols<RPT, NB> {
-  __device__ static inline void run(double (&)[RPT][NB], int, QrShared&, int) {}
-};
-
-// Writes this workgroup's Householder vectors (unit diagonal, zeros above)
-// and its T factor.
-template <int RPT>
-__device__ __forceinline__ void store_reflectors(const double (&a)[RPT][NB], int m, int w, double* Y,
-                                        int64_t ldy, double* Tout, const QrShared& sh, int tid) {
+  __syncthreads();  // Y written by this workgroup is read back below
+  // Gram matrix G = Y^T Y on the matrix cores: 16x16 tiles (ti, tj), ti <= tj;
+  // wavefront wid takes the 4-row steps k0 = 4 (wid + QW s).
+  const int lane = tid & 63, wid = tid >> 6, i16 = lane & 15, grp = lane >> 4;
+  constexpr int NT = NBT / 16;
+  d4v acc[NT][NT];
 #pragma unroll
-  for (int r = 0; r < RPT; ++r) {
-    const int t = tid + r * QT;
-    if (t < m) {
+  for (int i = 0; i < NT; ++i)
 #pragma unroll
-      for (int q = 0; q < NB; ++q)
-        if (q < w) Y[(int64_t)t * ldy + q] = t > q ? a[r][q] : (t == q ? 1.0 : 0.0);
+    for (int j = 0; j < NT; ++j) acc[i][j] = d4v{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+  for (int k0 = 4 * wid; k0 < m; k0 += 4 * QW) {
+    const int t = k0 + grp;
+    double y[NT];
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+      const int q = 16 * i + i16;
+      y[i] = (t < m && q < w) ? Y[(int64_t)t * ldy + q] : 0.0;
     }
+#pragma unroll
+    for (int i = 0; i < NT; ++i)
+#pragma unroll
+      for (int j = i; j < NT; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(y[i], y[j], acc[i][j], 0, 0, 0);
   }
-  for (int i = tid; i < NB * NB; i += QT) {
-    const int r = i / NB, cc = i % NB;
-    Tout[i] = (r < w && cc < w && cc >= r) ? sh.T[r][cc] : 0.0;
+  // result layout: register e of lane (grp, i16) holds row 4 e + grp, column i16
+#pragma unroll
+  for (int i = 0; i < NT; ++i)
+#pragma unroll
+    for (int j = i; j < NT; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) sh.Gp[wid][16 * i + 4 * e + grp][16 * j + i16] = acc[i][j][e];
+  __syncthreads();
+  for (int idx = tid; idx < NBT * NBT; idx += QT) {
+    const int i = idx / NBT, j = idx % NBT;
+    double g = 0.0;
+#pragma unroll
+    for (int v = 0; v < QW; ++v) g += sh.Gp[v][i][j];
+    sh.G[i][j] = g;  // valid for i, j in the computed (upper) tiles
+  }
+  __syncthreads();
+  // T = (diag(1/tau) + strictly-upper(G))^{-1}, by back substitution with
+  // one column of T per lane of wavefront 0.
+  if (tid < 64) {
+    const int j = tid;
+    double tc[NBT];
+#pragma unroll
+    for (int i = NBT - 1; i >= 0; --i) {
+      double s0 = i == j ? 1.0 : 0.0, s1 = 0.0;
+#pragma unroll
+      for (int k = i + 1; k < NBT; ++k) {
+        if ((k - i) & 1) s0 -= sh.G[i][k] * tc[k];
+        else s1 -= sh.G[i][k] * tc[k];
+      }
+      tc[i] = (i < w && j < w && i <= j) ? sh.tau[i] * (s0 + s1) : 0.0;
+    }
+    if (j < NBT) {
+#pragma unroll
+      for (int i = 0; i < NBT; ++i) Tout[i * NBT + j] = tc[i];
+    }
   }
 }
 
-template <int RL, int RT>
+template <int NBT, int RL, int RT>
 __global__ __launch_bounds__(QT) void qr_panel_kernel(double* __restrict__ A, int ld, int n, int j0,
                                                       int w, int rpl, int L, double* __restrict__ Y,
                                                       int ldy, double* __restrict__ Tl,
                                                       double* __restrict__ S, double* __restrict__ Yt,
                                                       double* __restrict__ Tt,
                                                       unsigned* __restrict__ counter) {
-  __shared__ QrShared sh;
+  __shared__ QrShared<NBT> sh;
   const int tid = threadIdx.x, leaf = blockIdx.x;
   const int r0 = j0 + leaf * rpl;
   const int m = min(rpl, n - r0);
   {
-    double a[RL][NB];
+    double a[RL][NBT];
 #pragma unroll
     for (int r = 0; r < RL; ++r) {
       const int t = tid + r * QT;
       const double* row = A + (int64_t)(r0 + t) * ld + j0;
 #pragma unroll
-      for (int q = 0; q < NB; ++q) a[r][q] = (t < m && q < w) ? row[q] : 0.0;
+      for (int q = 0; q < NBT; ++q) a[r][q] = (t < m && q < w) ? row[q] : 0.0;
     }
-    QrCols<RL, 0>::run(a, w, sh, tid);
-    __syncthreads();
-    store_reflectors<RL>(a, m, w, Y + (int64_t)r0 * ldy + j0, ldy, Tl + (int64_t)leaf * NB * NB, sh,
-                         tid);
-    if (L == 1) {
-      if (tid < w) {
-        double* row = A + (int64_t)(r0 + tid) * ld + j0;
-#pragma unroll
-        for (int q = 0; q < NB; ++q)
-          if (q < w) row[q] = q >= tid ? a[0][q] : 0.0;
-      }
-      return;
-    }
-    if (tid < w) {
-      double* srow = S + (int64_t)(leaf * w + tid) * NB;
-#pragma unroll
-      for (int q = 0; q < NB; ++q) srow[q] = (q >= tid && q < w) ? a[0][q] : 0.0;
-    }
+    double* Rd = L == 1 ? A + (int64_t)r0 * ld + j0 : S + (int64_t)leaf * w * NBT;
+    const int64_t ldr = L == 1 ? ld : NBT;
+    local_qr<NBT, RL>(a, m, w, sh, tid, Y + (int64_t)r0 * ldy + j0, ldy, Rd, ldr,
+                      Tl + (int64_t)leaf * NBT * NBT);
   }
+  if (L == 1) return;
   // Publish the stacked factor; the last leaf to arrive factors the stack.
   __threadfence();
   __syncthreads();
@@ -214,44 +342,42 @@ __global__ __launch_bounds__(QT) void qr_panel_kernel(double* __restrict__ A, in
   if (!sh.last) return;
   __threadfence();
   const int Sm = L * w;
-  double b[RT][NB];
+  double b[RT][NBT];
 #pragma unroll
   for (int r = 0; r < RT; ++r) {
     const int t = tid + r * QT;
 #pragma unroll
-    for (int q = 0; q < NB; ++q) b[r][q] = (t < Sm && q < w) ? S[(int64_t)t * NB + q] : 0.0;
+    for (int q = 0; q < NBT; ++q) b[r][q] = (t < Sm && q < w) ? S[(int64_t)t * NBT + q] : 0.0;
   }
-  QrCols<RT, 0>::run(b, w, sh, tid);
-  __syncthreads();
-  store_reflectors<RT>(b, Sm, w, Yt, NB, Tt, sh, tid);
-  if (tid < w) {
-    double* row = A + (int64_t)(j0 + tid) * ld + j0;
-#pragma unroll
-    for (int q = 0; q < NB; ++q)
-      if (q < w) row[q] = q >= tid ? b[0][q] : 0.0;
-  }
+  local_qr<NBT, RT>(b, Sm, w, sh, tid, Yt, NBT, A + (int64_t)j0 * ld + j0, ld, Tt);
   if (tid == 0) atomicExch(counter, 0u);
 }
 
-constexpr int AT = 256;   // threads of the apply workgroups
-constexpr int ACW = 32;   // columns per workgroup
-constexpr int ART = 64;   // rows per LDS tile
+constexpr int AT = 1024;  // threads of the apply workgroups (16 wavefronts)
+constexpr int AW = AT / 64;
+constexpr int ACW = 16;   // columns per workgroup
 
-// B <- (I - Y op(T) Y^T) B on columns [c0, c1), op(T) = T^T if TRANS.  Leaf
-// mode (STACKED = false): workgroup x handles leaf x, rows [j0 + x rpl, ...)
-// of B, reflectors Y[row][j0 + q] (leading dimension ldy), T = Tsrc + x NB^2.
-// Stacked mode: the L*w stacked rows (leaf i, offset t) -> row j0 + i rpl + t,
-// reflectors Ysrc[(i w + t) NB + q], T = Tsrc.
-template <bool STACKED, bool TRANS>
+// B <- (I - Y op(T) Y^T) B on columns [c0, c1), op(T) = T^T if TRANS, on the
+// FP64 matrix cores (16x16x4).  Leaf mode (STACKED = false): workgroup x
+// handles leaf x, rows [j0 + x rpl, ...) of B, reflectors Y[row][j0 + q]
+// (leading dimension ldy), T = Tsrc + x NBT^2.  Stacked mode: the L*w stacked
+// rows (leaf i, offset t) -> row j0 + i rpl + t, reflectors
+// Ysrc[(i w + t) NBT + q], T = Tsrc.  Each workgroup owns 16 columns:
+//   W = Y^T B (NBT x 16): the wavefronts split the rows, partial tiles are
+//       summed in LDS in a fixed order;
+//   W <- op(T) W;
+//   B <- B - Y W: 16-row tiles distributed over the wavefronts.
+template <int NBT, bool STACKED, bool TRANS>
 __global__ __launch_bounds__(AT) void qr_apply_kernel(double* __restrict__ B, int ldb, int c0, int c1,
                                                       const double* __restrict__ Ysrc, int ldy,
                                                       const double* __restrict__ Tsrc, int n, int j0,
                                                       int w, int rpl, int L) {
-  __shared__ double Ys[ART][NB + 1];
-  __shared__ double Bs[ART][ACW + 1];
-  __shared__ double W[NB][ACW + 1];
-  __shared__ double Tsh[NB][NB + 1];
-  const int tid = threadIdx.x;
+  constexpr int NT = NBT / 16;
+  __shared__ double Wp[AW][NBT][ACW + 1];
+  __shared__ double W[NBT][ACW + 1];
+  __shared__ double Tsh[NBT][NBT + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int i16 = lane & 15, grp = lane >> 4;
   int rows, rbase = 0;
   const double* Yb;
   const double* T;
@@ -259,98 +385,83 @@ __global__ __launch_bounds__(AT) void qr_apply_kernel(double* __restrict__ B, in
   if (STACKED) {
     rows = L * w;
     Yb = Ysrc;
-    ys = NB;
+    ys = NBT;
     T = Tsrc;
   } else {
     rbase = j0 + blockIdx.x * rpl;
     rows = min(rpl, n - rbase);
     Yb = Ysrc + (int64_t)rbase * ldy + j0;
     ys = ldy;
-    T = Tsrc + (int64_t)blockIdx.x * NB * NB;
+    T = Tsrc + (int64_t)blockIdx.x * NBT * NBT;
   }
   const int cb = c0 + blockIdx.y * ACW;
-  const int nc = min(ACW, c1 - cb);
+  const int col = cb + i16;
+  const bool colok = col < c1;
   auto grow = [&](int r) -> int64_t {
     return STACKED ? (int64_t)(j0 + (r / w) * rpl + r % w) : (int64_t)(rbase + r);
   };
-  auto load_tiles = [&](int r0) {
-    for (int i = tid; i < ART * NB; i += AT) {
-      const int rr = i / NB, q = i % NB, r = r0 + rr;
-      Ys[rr][q] = (r < rows && q < w) ? Yb[(int64_t)r * ys + q] : 0.0;
-    }
-    for (int i = tid; i < ART * ACW; i += AT) {
-      const int rr = i / ACW, j = i % ACW, r = r0 + rr;
-      Bs[rr][j] = (r < rows && j < nc) ? B[grow(r) * ldb + cb + j] : 0.0;
-    }
+  auto yat = [&](int r, int q) -> double {
+    return (r < rows && q < w) ? Yb[(int64_t)r * ys + q] : 0.0;
   };
-  for (int i = tid; i < NB * NB; i += AT) Tsh[i / NB][i % NB] = T[i];
-  // W = Y^T B: thread (tq, tj) owns rows 2tq, 2tq+1 and columns 2tj, 2tj+1 of W
-  const int tq = tid / 16, tj = tid % 16;
-  double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
-  for (int r0 = 0; r0 < rows; r0 += ART) {
-    load_tiles(r0);
-    __syncthreads();
-#pragma unroll 8
-    for (int rr = 0; rr < ART; ++rr) {
-      const double y0 = Ys[rr][2 * tq], y1 = Ys[rr][2 * tq + 1];
-      const double b0 = Bs[rr][2 * tj], b1 = Bs[rr][2 * tj + 1];
-      acc[0][0] += y0 * b0;
-      acc[0][1] += y0 * b1;
-      acc[1][0] += y1 * b0;
-      acc[1][1] += y1 * b1;
-    }
-    __syncthreads();
+  auto bat = [&](int r) -> double { return (r < rows && colok) ? B[grow(r) * ldb + col] : 0.0; };
+  for (int i = tid; i < NBT * NBT; i += AT) Tsh[i / NBT][i % NBT] = T[i];
+
+  // W = Y^T B: wavefront wv takes the 4-row steps k0 = 4 (wv + AW s)
+  d4v acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = d4v{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+  for (int k0 = 4 * wv; k0 < rows; k0 += 4 * AW) {
+    const int r = k0 + grp;
+    const double b = bat(r);
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+      acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(yat(r, 16 * t + i16), b, acc[t], 0, 0, 0);
   }
+  // result layout: register e of lane (grp, i16) holds row 4 e + grp, column i16
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int t = 0; t < NT; ++t)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) W[2 * tq + a][2 * tj + b] = acc[a][b];
+    for (int e = 0; e < 4; ++e) Wp[wv][16 * t + 4 * e + grp][i16] = acc[t][e];
+  __syncthreads();
+  if (tid < NBT * ACW) {
+    const int q = tid / ACW, j = tid % ACW;
+    double s = 0.0;
+#pragma unroll
+    for (int v = 0; v < AW; ++v) s += Wp[v][q][j];
+    W[q][j] = s;
+  }
   __syncthreads();
   // W <- op(T) W (T upper triangular)
-  double w2[2][2];
-#pragma unroll
-  for (int a = 0; a < 2; ++a) {
-    const int q = 2 * tq + a;
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const int j = 2 * tj + b;
-      double s = 0.0;
-      if (TRANS) {
-        for (int i = 0; i <= q; ++i) s += Tsh[i][q] * W[i][j];
-      } else {
-        for (int i = q; i < NB; ++i) s += Tsh[q][i] * W[i][j];
-      }
-      w2[a][b] = s;
+  double w2 = 0.0;
+  if (tid < NBT * ACW) {
+    const int q = tid / ACW, j = tid % ACW;
+    if (TRANS) {
+      for (int p = 0; p <= q; ++p) w2 += Tsh[p][q] * W[p][j];
+    } else {
+      for (int p = q; p < NBT; ++p) w2 += Tsh[q][p] * W[p][j];
     }
   }
   __syncthreads();
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) W[2 * tq + a][2 * tj + b] = w2[a][b];
+  if (tid < NBT * ACW) W[tid / ACW][tid % ACW] = w2;
   __syncthreads();
-  // B <- B - Y W: thread owns row tid/4 of the tile and 8 columns
-  const int rr = tid / 4, jb = (tid % 4) * 8;
-  for (int r0 = 0; r0 < rows; r0 += ART) {
-    load_tiles(r0);
-    __syncthreads();
-    double o[8];
+  // B <- B - Y W on 16-row tiles: A operand Y[r0 + i16][k], B operand W[k][i16]
+  double wop[NBT / 4];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) o[j] = Bs[rr][jb + j];
-#pragma unroll 4
-    for (int q = 0; q < NB; ++q) {
-      const double y = Ys[rr][q];
+  for (int s = 0; s < NBT / 4; ++s) wop[s] = W[4 * s + grp][i16];
+  for (int r0 = 16 * wv; r0 < rows; r0 += 16 * AW) {
+    d4v acc3 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int j = 0; j < 8; ++j) o[j] -= y * W[q][jb + j];
+    for (int s = 0; s < NBT / 4; ++s)
+      acc3 = __builtin_amdgcn_mfma_f64_16x16x4f64(yat(r0 + i16, 4 * s + grp), wop[s], acc3, 0, 0, 0);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int r = r0 + 4 * e + grp;
+      if (r < rows && colok) {
+        double* dst = B + grow(r) * ldb + col;
+        *dst = *dst - acc3[e];
+      }
     }
-    const int r = r0 + rr;
-    if (r < rows) {
-      double* dst = B + grow(r) * ldb + cb + jb;
-#pragma unroll
-      for (int j = 0; j < 8; ++j)
-        if (jb + j < nc) dst[j] = o[j];
-    }
-    __syncthreads();
   }
 }
 
@@ -367,36 +478,50 @@ __global__ void zero_u32_kernel(unsigned* p, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
 }
 
-int panels_of(int k) { return (int)cdiv(k, NB); }
+int nb_of(int n) { return n > 8192 ? 16 : 32; }
+int panels_of(int n, int k) { return (int)cdiv(k, nb_of(n)); }
+int max_panels(int k) { return (int)cdiv(k, 16); }
+
+// Offsets of panel `panel` in the per-panel workspace arrays.
+double* tl_of(const QrWork& w, int nb, int panel) {
+  return w.Tl + (int64_t)panel * QR_MAX_LEAVES * nb * nb;
+}
+double* yt_of(const QrWork& w, int nb, int panel) {
+  return w.Yt + (int64_t)panel * QR_MAX_LEAVES * nb * nb;
+}
+double* tt_of(const QrWork& w, int nb, int panel) { return w.Tt + (int64_t)panel * nb * nb; }
 
 void launch_panel(hipStream_t s, const QrPanel& p, double* A, int ld, int n, QrWork& w,
                   int panel) {
-  double* Tl = w.Tl + (int64_t)panel * QR_MAX_LEAVES * NB * NB;
-  double* Yt = w.Yt + (int64_t)panel * QR_MAX_STACK * NB;
-  double* Tt = w.Tt + (int64_t)panel * NB * NB;
+  double* Tl = tl_of(w, p.nb, panel);
+  double* Yt = yt_of(w, p.nb, panel);
+  double* Tt = tt_of(w, p.nb, panel);
   unsigned* cnt = w.counter + panel;
   const dim3 grid(p.L);
-#define CTM_QR_PANEL(RL, RT)                                                                  \
-  qr_panel_kernel<RL, RT><<<grid, QT, 0, s>>>(A, ld, n, p.j0, p.w, p.rpl, p.L, w.Y, w.k, Tl, \
-                                               w.S, Yt, Tt, cnt)
-  if (p.rpt_leaf == 1 && p.rpt_tree == 1) CTM_QR_PANEL(1, 1);
-  else if (p.rpt_leaf == 1) CTM_QR_PANEL(1, 2);
-  else if (p.rpt_tree == 1) CTM_QR_PANEL(2, 1);
-  else CTM_QR_PANEL(2, 2);
+#define CTM_QR_PANEL(NBT, RL, RT)                                                            \
+  qr_panel_kernel<NBT, RL, RT><<<grid, QT, 0, s>>>(A, ld, n, p.j0, p.w, p.rpl, p.L, w.Y, w.k, \
+                                                    Tl, w.S, Yt, Tt, cnt)
+  if (p.nb == 32) {
+    if (p.rpt_leaf == 1) CTM_QR_PANEL(32, 1, 1);
+    else if (p.rpt_tree == 1) CTM_QR_PANEL(32, 2, 1);
+    else CTM_QR_PANEL(32, 2, 2);
+  } else {
+    if (p.rpt_tree == 1) CTM_QR_PANEL(16, 4, 1);
+    else CTM_QR_PANEL(16, 4, 2);
+  }
 #undef CTM_QR_PANEL
   CTM_LAUNCHED();
 }
 
-void launch_apply(hipStream_t s, bool stacked, bool trans, const QrPanel& p, double* B, int ldb,
-                  int c0, int c1, int n, const QrWork& w, int panel) {
-  if (c1 <= c0) return;
+template <int NBT>
+void launch_apply_nb(hipStream_t s, bool stacked, bool trans, const QrPanel& p, double* B, int ldb,
+                     int c0, int c1, int n, const QrWork& w, int panel) {
   const dim3 grid(stacked ? 1 : p.L, (unsigned)cdiv(c1 - c0, ACW));
-  const double* Y = stacked ? w.Yt + (int64_t)panel * QR_MAX_STACK * NB : w.Y;
-  const double* T = stacked ? w.Tt + (int64_t)panel * NB * NB
-                            : w.Tl + (int64_t)panel * QR_MAX_LEAVES * NB * NB;
-#define CTM_QR_APPLY(ST, TR)                                                                    \
-  qr_apply_kernel<ST, TR><<<grid, AT, 0, s>>>(B, ldb, c0, c1, Y, w.k, T, n, p.j0, p.w, p.rpl, \
-                                              p.L)
+  const double* Y = stacked ? yt_of(w, NBT, panel) : w.Y;
+  const double* T = stacked ? tt_of(w, NBT, panel) : tl_of(w, NBT, panel);
+#define CTM_QR_APPLY(ST, TR)                                                                  \
+  qr_apply_kernel<NBT, ST, TR><<<grid, AT, 0, s>>>(B, ldb, c0, c1, Y, w.k, T, n, p.j0, p.w, \
+                                                   p.rpl, p.L)
   if (stacked && trans) CTM_QR_APPLY(true, true);
   else if (stacked) CTM_QR_APPLY(true, false);
   else if (trans) CTM_QR_APPLY(false, true);
@@ -405,17 +530,28 @@ void launch_apply(hipStream_t s, bool stacked, bool trans, const QrPanel& p, dou
   CTM_LAUNCHED();
 }
 
+void launch_apply(hipStream_t s, bool stacked, bool trans, const QrPanel& p, double* B, int ldb,
+                  int c0, int c1, int n, const QrWork& w, int panel) {
+  if (c1 <= c0) return;
+  if (p.nb == 32) launch_apply_nb<32>(s, stacked, trans, p, B, ldb, c0, c1, n, w, panel);
+  else launch_apply_nb<16>(s, stacked, trans, p, B, ldb, c0, c1, n, w, panel);
+}
+
 }  // namespace
 
+// Per-panel arrays are sized for the larger of the two panel widths:
+// ceil(k/16) panels of width 16 need at most as much as ceil(k/32) of 32.
 size_t qr_work_bytes(int n, int k) {
-  const int64_t P = panels_of(k);
-  const int64_t doubles = (int64_t)n * k + P * QR_MAX_LEAVES * NB * NB + P * QR_MAX_STACK * NB +
-                          P * NB * NB + (int64_t)QR_MAX_STACK * NB;
+  const int64_t P = max_panels(k);
+  const int64_t per_panel = (int64_t)QR_MAX_LEAVES * QR_NB_MAX * QR_NB_MAX;
+  const int64_t doubles = (int64_t)n * k + 2 * P * per_panel + P * QR_NB_MAX * QR_NB_MAX +
+                          (int64_t)QR_MAX_STACK * QR_NB_MAX;
   return (size_t)doubles * sizeof(double) + (size_t)P * sizeof(unsigned) + 256;
 }
 
 QrWork qr_work_carve(hipStream_t s, void* p, int n, int k) {
-  const int64_t P = panels_of(k);
+  const int64_t P = max_panels(k);
+  const int64_t per_panel = (int64_t)QR_MAX_LEAVES * QR_NB_MAX * QR_NB_MAX;
   QrWork w;
   w.n = n;
   w.k = k;
@@ -423,13 +559,13 @@ QrWork qr_work_carve(hipStream_t s, void* p, int n, int k) {
   w.Y = d;
   d += (int64_t)n * k;
   w.Tl = d;
-  d += P * QR_MAX_LEAVES * NB * NB;
+  d += P * per_panel;
   w.Yt = d;
-  d += P * QR_MAX_STACK * NB;
+  d += P * per_panel;
   w.Tt = d;
-  d += P * NB * NB;
+  d += P * QR_NB_MAX * QR_NB_MAX;
   w.S = d;
-  d += (int64_t)QR_MAX_STACK * NB;
+  d += (int64_t)QR_MAX_STACK * QR_NB_MAX;
   w.counter = (unsigned*)d;
   zero_u32_kernel<<<1, 256, 0, s>>>(w.counter, (int)P);
   CTM_LAUNCHED();
@@ -438,10 +574,11 @@ QrWork qr_work_carve(hipStream_t s, void* p, int n, int k) {
 
 QrPanel qr_panel_plan(int n, int k, int j0) {
   QrPanel p;
+  p.nb = nb_of(n);
   p.j0 = j0;
-  p.w = std::min(NB, k - j0);
+  p.w = std::min(p.nb, k - j0);
   const int m = n - j0;
-  p.rpt_leaf = m > 8192 ? 2 : 1;
+  p.rpt_leaf = p.nb == 32 ? (m <= QT ? 1 : 2) : 4;
   const int b = QT * p.rpt_leaf;
   p.L = (int)cdiv(m, b);
   p.rpl = (int)cdiv(m, p.L);
@@ -453,8 +590,11 @@ void householder_qr(hipStream_t s, double* M, int ld, int n, int k, QrWork& w) {
   if (n < k || k < 1) throw std::invalid_argument("householder_qr: needs n >= k >= 1");
   if (n > QR_MAX_ROWS) throw std::invalid_argument("householder_qr: n > 32768");
   if (n > w.n || k != w.k) throw std::invalid_argument("householder_qr: workspace shape mismatch");
-  for (int panel = 0, j0 = 0; j0 < k; ++panel, j0 += NB) {
+  const int nb = nb_of(n);
+  for (int panel = 0, j0 = 0; j0 < k; ++panel, j0 += nb) {
     const QrPanel p = qr_panel_plan(n, k, j0);
+    if (p.L > QR_MAX_LEAVES || p.L * p.w > QT * 2 || p.rpl < p.w)
+      throw std::logic_error("householder_qr: bad panel plan");
     launch_panel(s, p, M, ld, n, w, panel);
     const int c0 = j0 + p.w;
     if (c0 >= k) continue;
@@ -467,8 +607,8 @@ void householder_form_q(hipStream_t s, const QrWork& w, int n, int k, double* Q,
   fill_eye_kernel<<<(unsigned)std::min<int64_t>(4096, cdiv((int64_t)n * k, 256)), 256, 0, s>>>(
       Q, n, k, ldq);
   CTM_LAUNCHED();
-  for (int panel = panels_of(k) - 1; panel >= 0; --panel) {
-    const QrPanel p = qr_panel_plan(n, k, panel * NB);
+  for (int panel = panels_of(n, k) - 1; panel >= 0; --panel) {
+    const QrPanel p = qr_panel_plan(n, k, panel * nb_of(n));
     if (p.L > 1) launch_apply(s, true, false, p, Q, ldq, p.j0, k, n, w, panel);
     launch_apply(s, false, false, p, Q, ldq, p.j0, k, n, w, panel);
   }
