@@ -119,6 +119,32 @@ int ctm_converge(ctm_ctx *c, double tol, int max_steps, int n_check, int *steps_
  * Errors: CTM_EINVAL, CTM_ENONFINITE, CTM_EDEVICE. */
 int ctm_energy(ctm_ctx *c, const double *h_host, double *e_host, double *rho_host);
 
+/* Energy gradient with respect to the site tensor (Sec. II.D: the energy
+ * differentiated through the CTMRG environment; the one-step adjoint of the
+ * corner and edge contractions, of the two QR factorizations and of the
+ * normalizations is written out as matrix products, all in FP64).
+ * Needs a truncated environment (chi_c = chi < chi D^2, after at least one
+ * truncating step), else CTM_ESTATE.  h_host: the d^2 x d^2 operator as for
+ * ctm_energy; E = Tr(rho h)/Tr(rho).
+ *  mode = k > 0: runs k CTMRG steps from the current state, evaluates E on
+ *    the result and differentiates through the k steps with the current
+ *    state held fixed (the paper's tracked steps); (C_i, T_i, P_i) of every
+ *    step are kept and the step's intermediates recomputed on the way back.
+ *    The state of the context is not changed.
+ *  mode = 0: fixed-point adjoint at the current state, which must be a
+ *    stationary point of the iteration (converged with ctm_converge):
+ *    dE/dA = dE/dA|_env + sum_j (dF/dA)^T (J^T)^j dE/d(env), J the step's
+ *    Jacobian; terms are added until one changes the cotangent of the
+ *    double layer by less than tol relative to its norm (CTM_ENOTCONV after
+ *    max_iter terms; the gradient is still written).
+ * gradA_dev: d*D^3 FP64 device buffer, receives the projection of dE/dA onto
+ * the C3v-symmetric subspace.  e_host (nullable): E.  iters_host (nullable):
+ * adjoint steps taken.  Allocates its workspace (about nine (chi D^2)^2 FP64
+ * arrays) at the first call.  Errors: CTM_EINVAL, CTM_ESTATE, CTM_ENOTCONV,
+ * CTM_ENONFINITE, CTM_ENOMEM, CTM_EDEVICE. */
+int ctm_grad(ctm_ctx *c, const double *h_host, int mode, double tol, int max_iter,
+             double *gradA_dev, double *e_host, int *iters_host);
+
 /* Normalized corner spectrum of the current state: |eigenvalues| of C in
  * decreasing order divided by the largest.  s_host must hold chi values;
  * n_host receives chi_c.  Synchronizes.  Errors: CTM_EINVAL, CTM_EDEVICE. */

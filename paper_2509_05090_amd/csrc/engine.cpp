@@ -43,6 +43,7 @@
 #include "kernels.hpp"
 #include "qr.hpp"
 #include "spectrum.hpp"
+#include "context.hpp"
 
 using namespace ctm;
 
@@ -50,88 +51,11 @@ namespace {
 
 thread_local std::string g_error;
 
-struct OutOfMemory : std::runtime_error {
-  explicit OutOfMemory(const std::string& s) : std::runtime_error(s) {}
-};
-
 }  // namespace
 
 namespace ctm {
 void set_global_error(const std::string& s) { g_error = s; }
 }  // namespace ctm
-
-struct ctm_ctx {
-  ctm_config cfg{};
-  hipStream_t stream = nullptr;
-  std::string err;
-  bool poisoned = false;
-  int d = 0, D = 0, D2 = 0, chi = 0;
-  int64_t nmax = 0;
-  int chi_c = 1, steps = 0, p_rows = 0;
-  DType prec = DType::F64;
-
-  std::vector<void*> allocations;
-
-  // FP64 state and inputs
-  double *A = nullptr, *a = nullptr, *aO = nullptr, *aOr = nullptr, *G = nullptr;
-  double *C = nullptr, *T = nullptr, *Cn = nullptr, *Tn = nullptr, *P = nullptr;
-  // FP64 work
-  double *M = nullptr, *Q = nullptr, *Cp = nullptr, *Tp = nullptr, *Xs = nullptr, *Xq = nullptr;
-  double *sgn = nullptr, *sumsq = nullptr, *dev_small = nullptr;
-  int* flag = nullptr;
-  // Intermediates; allocated with 8-byte elements so that they hold any precision.
-  void *aE = nullptr, *CE = nullptr, *TE = nullptr, *PE = nullptr, *QE = nullptr;
-  void *TCp = nullptr, *V = nullptr, *W = nullptr, *Ct = nullptr, *Gm = nullptr, *V2 = nullptr;
-  // energy
-  double *XO = nullptr, *EO = nullptr, *Cr2 = nullptr, *Cr4 = nullptr, *Cr5 = nullptr;
-  double *rho_raw = nullptr, *h_dev = nullptr, *e_out = nullptr;
-  QrWork qr;
-  Scratch ws;
-
-  // spectrum cache (host)
-  std::vector<double> spec;
-  int spec_step = -1;
-
-  // stage timing (HIP events on the stream)
-  struct TimedInterval {
-    int stage;
-    hipEvent_t begin, end;
-  };
-  bool prof_on = false, prof_active = false;
-  std::vector<hipEvent_t> event_pool;
-  size_t events_used = 0;
-  std::vector<TimedInterval> intervals;
-  double big_flops = 0.0;
-  hipEvent_t stage_open[CTM_NSTAGES] = {};
-
-  hipEvent_t next_event() {
-    if (events_used == event_pool.size()) {
-      hipEvent_t e;
-      CTM_HIP(hipEventCreate(&e));
-      event_pool.push_back(e);
-    }
-    return event_pool[events_used++];
-  }
-
-  void* alloc(size_t bytes) {
-    void* p = nullptr;
-    if (bytes == 0) bytes = 8;
-    hipError_t e = hipMalloc(&p, bytes);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      throw OutOfMemory("hipMalloc(" + std::to_string(bytes) + ") failed: " + hipGetErrorString(e));
-    }
-    allocations.push_back(p);
-    return p;
-  }
-  double* allocd(int64_t n) { return (double*)alloc((size_t)n * sizeof(double)); }
-
-  ~ctm_ctx() {
-    if (stream) (void)hipStreamSynchronize(stream);
-    for (hipEvent_t e : event_pool) (void)hipEventDestroy(e);
-    for (void* p : allocations) (void)hipFree(p);
-  }
-};
 
 namespace {
 
@@ -393,7 +317,9 @@ int do_steps(ctm_ctx* c, int n_steps, double* delta) {
   return CTM_OK;
 }
 
-void ensure_energy_buffers(ctm_ctx* c) {
+}  // namespace
+
+void ctm::ensure_energy_buffers(ctm_ctx* c) {
   if (c->XO) return;
   const int64_t x2 = (int64_t)c->chi * c->chi;
   const int64_t dd = (int64_t)c->d * c->d;
@@ -410,6 +336,8 @@ void ensure_energy_buffers(ctm_ctx* c) {
   launch_double_layer_open(c->stream, c->A, c->d, c->D, 0, c->aO);
   launch_double_layer_open(c->stream, c->A, c->d, c->D, 1, c->aOr);
 }
+
+namespace {
 
 // Bond density matrix of the apex pair on the six-corner ring (FP64).
 int do_energy(ctm_ctx* c, const double* h_host, double* e_host, double* rho_host) {
@@ -656,6 +584,13 @@ int ctm_energy(ctm_ctx* c, const double* h_host, double* e_host, double* rho_hos
   return guarded(c, [&]() -> int {
     if (!h_host) throw std::invalid_argument("null operator");
     return do_energy(c, h_host, e_host, rho_host);
+  });
+}
+
+int ctm_grad(ctm_ctx* c, const double* h_host, int mode, double tol, int max_iter,
+             double* gradA_dev, double* e_host, int* iters_host) {
+  return guarded(c, [&]() -> int {
+    return do_grad(c, h_host, mode, tol, max_iter, gradA_dev, e_host, iters_host);
   });
 }
 

@@ -31,7 +31,7 @@ PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
 DTYPE_CODE = {"float64": 0, "float32": 1, "bfloat16": 2}
 
 EXPORTS = ("ctm_symmetrize", "ctm_init", "ctm_step", "ctm_converge", "ctm_energy",
-           "ctm_spectrum", "ctm_query", "ctm_get_env", "ctm_set_env", "ctm_set_precision",
+           "ctm_grad", "ctm_spectrum", "ctm_query", "ctm_get_env", "ctm_set_env", "ctm_set_precision",
            "ctm_free", "ctm_last_error", "ctm_gemm", "ctm_qr", "ctm_profile",
            "ctm_profile_read")
 STAGES = ("corner", "projector", "renorm_c", "renorm_t", "big_gemm")
@@ -60,6 +60,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "ctm_step": (i, [vp, i, pd]),
         "ctm_converge": (i, [vp, d, i, i, pi, pd]),
         "ctm_energy": (i, [vp, pd, pd, pd]),
+        "ctm_grad": (i, [vp, pd, i, d, i, vp, pd, pi]),
         "ctm_spectrum": (i, [vp, pd, pi]),
         "ctm_query": (i, [vp, pi, pi, pi]),
         "ctm_get_env": (i, [vp, vp, vp, vp]),
@@ -187,6 +188,20 @@ class Context:
                self._h)
         return e.value, rho
 
+    def grad(self, h: np.ndarray, mode: int = 0, tol: float = 1e-12, max_iter: int = 100000):
+        """ctm_grad: (g, E, adjoint steps, converged); g is a (d, D, D, D)
+        float64 GPU tensor, the symmetric projection of dE/dA."""
+        import torch
+        dd = self.d * self.d
+        h = np.ascontiguousarray(h, dtype=np.float64).reshape(dd, dd)
+        g = torch.empty((self.d, self.D, self.D, self.D), dtype=torch.float64, device="cuda")
+        e = ctypes.c_double(math.nan)
+        it = ctypes.c_int(0)
+        code = _check(_lib.ctm_grad(self._h, h.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    int(mode), float(tol), int(max_iter), _ptr(g), ctypes.byref(e),
+                                    ctypes.byref(it)), self._h, allow=(CTM_ENOTCONV,))
+        return g, e.value, it.value, code == CTM_OK
+
     def spectrum(self) -> np.ndarray:
         s = np.zeros(self.chi)
         n = ctypes.c_int(0)
@@ -230,3 +245,33 @@ class Context:
 
     def set_precision(self, prec: str):
         _check(_lib.ctm_set_precision(self._h, PREC[prec]), self._h)
+
+
+def _energy_function():
+    import torch
+
+    class CtmEnergy(torch.autograd.Function):
+        """E(A) = Tr(rho h) on the converged QR-CTMRG environment of the
+        C3v-symmetric site tensor A; backward multiplies the incoming
+        gradient by ctm_grad's fixed-point gradient (symmetric projection of
+        dE/dA).  forward(A, G, chi, h, tol, max_steps)."""
+
+        @staticmethod
+        def forward(ctx, A, G, chi, h, tol=1e-12, max_steps=20000):
+            with Context(A.detach().contiguous(), G, chi) as c:
+                c.converge(tol, max_steps, n_check=10)
+                g, e, _, _ = c.grad(h, mode=0, tol=tol)
+            ctx.save_for_backward(g)
+            return torch.tensor(e, dtype=A.dtype, device=A.device)
+
+        @staticmethod
+        def backward(ctx, gE):
+            (g,) = ctx.saved_tensors
+            return gE * g, None, None, None, None, None
+
+    return CtmEnergy
+
+
+def energy(A, G, chi, h, tol=1e-12, max_steps=20000):
+    """Differentiable converged CTMRG energy (torch.autograd.Function)."""
+    return _energy_function().apply(A, G, chi, h, tol, max_steps)

@@ -25,7 +25,7 @@ import numpy as np  # noqa: E402
 import ctm_inputs as ci  # noqa: E402
 from oracle import ctm  # noqa: E402
 
-MAX_STEPS = {"c1": 50, "c2": 3000, "c3": 1200, "c4": 3000}
+MAX_STEPS = {"c1": 50, "c2": 3000, "c3": 4000, "c4": 3000}
 CHECKPOINTS = (10, 20, 50, 100, 200, 400)
 PROJECTORS = {"c1": ("qr",), "c2": ("qr", "evd"), "c3": ("qr",), "c4": ("qr",)}
 

@@ -21,8 +21,8 @@ def declared_functions():
 
 def test_headers_declare_the_boundary():
     names = declared_functions()
-    for required in ("ctm_init", "ctm_step", "ctm_converge", "ctm_energy", "ctm_free",
-                     "ctm_last_error", "ctm_symmetrize", "ctm_spectrum"):
+    for required in ("ctm_init", "ctm_step", "ctm_converge", "ctm_energy", "ctm_grad",
+                     "ctm_free", "ctm_last_error", "ctm_symmetrize", "ctm_spectrum"):
         assert required in names
 
 
@@ -53,4 +53,5 @@ def test_argument_errors_without_device_work():
     assert lib.ctm_init(ctypes.byref(h), ctypes.byref(evd), ctypes.c_void_p(8),
                         ctypes.c_void_p(8), None) == ctm.CTM_EINVAL
     assert lib.ctm_symmetrize(None, None, 2, 2, None) == ctm.CTM_EINVAL
+    assert lib.ctm_grad(None, None, 0, 1e-12, 10, None, None, None) == ctm.CTM_EINVAL
     lib.ctm_free(None)
