@@ -55,8 +55,14 @@ enum {
  *               per step: at a fixed point Q spans a dominant eigenspace of
  *               the enlarged corner Ct.  The first projector of an n-row
  *               corner is gs(first n rows of G).
- * CTM_PROJ_EVD: eigenvectors of Ct of the chi largest |eigenvalues|
- *               (Fig. 3c).  Reserved; not implemented by this library yet. */
+ * CTM_PROJ_EVD: eigenvectors of Ct of the chi largest |eigenvalues| (Fig. 3c),
+ *               ordered by decreasing |eigenvalue|, then larger eigenvalue;
+ *               column signs follow P_prev when it matches n, else each
+ *               column's largest entry is positive.  FP64 Householder
+ *               tridiagonalization on the GPU, the tridiagonal eigenpairs on
+ *               the host (bisection, inverse iteration), back-transformation
+ *               on the GPU; the baseline the QR projector replaces.  Needs
+ *               chi*D^2 <= 8192; synchronizes once per step. */
 typedef enum { CTM_PROJ_QR = 0, CTM_PROJ_EVD = 1 } ctm_proj;
 
 /* Arithmetic of the contractions.  The QR, the sign gauge, the

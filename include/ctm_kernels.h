@@ -40,6 +40,16 @@ int ctm_gemm(int prec, int M, int N, int K,
  * convention R[j][j] = -sign(pivot) * ||column||.  M_dev is not modified. */
 int ctm_qr(const double *M_dev, int n, int k, double *Q_dev, double *R_dev, void *stream);
 
+/* Eigenvectors of the k eigenvalues of largest magnitude of the symmetric
+ * n x n FP64 matrix A_dev (row-major, 1 <= k <= n <= 8192; the
+ * eigendecomposition projector's solver, Sec. II.B, Fig. 3c).  U_dev (n x k)
+ * receives them ordered by decreasing |eigenvalue|, then larger eigenvalue;
+ * column signs: non-negative overlap with P_dev's columns (n x k, nullable),
+ * else largest entry positive.  lam_host (k) receives the eigenvalues.
+ * A_dev is not modified.  Synchronizes. */
+int ctm_eigh(const double *A_dev, int n, int k, const double *P_dev, double *U_dev,
+             double *lam_host, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

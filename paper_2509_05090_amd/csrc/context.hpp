@@ -8,6 +8,7 @@
 #include "ctm.h"
 #include "gemm.hpp"
 #include "qr.hpp"
+#include "evd.hpp"
 
 namespace ctm {
 
@@ -50,6 +51,7 @@ struct ctm_ctx {
   double *XO = nullptr, *EO = nullptr, *Cr2 = nullptr, *Cr4 = nullptr, *Cr5 = nullptr;
   double *rho_raw = nullptr, *h_dev = nullptr, *e_out = nullptr;
   QrWork qr;
+  ctm::EvdWork evd;  // eigendecomposition projector (CTM_PROJ_EVD only)
   Scratch ws;
   ctm::GradBuffers* grad = nullptr;  // adjoint workspace, allocated by the first ctm_grad
 

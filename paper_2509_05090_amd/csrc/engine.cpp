@@ -232,6 +232,27 @@ void qr_projector(ctm_ctx* c, DType e, bool update) {
     CTM_HIP(hipMemcpyAsync(c->P, c->Q, (size_t)n * chi * sizeof(double), hipMemcpyDeviceToDevice, s));
 }
 
+// Projector of the eigendecomposition rule (Fig. 3c) into c->Q: the chi
+// eigenvectors of Ct of largest |eigenvalue|, column signs following P_prev
+// when it matches n (else largest entry positive).  If update, P_prev <- Q.
+void evd_projector(ctm_ctx* c, DType e, bool update) {
+  const int chi = c->chi;
+  const int n = c->chi_c * c->D2;
+  const double* Pref = c->p_rows == n ? c->P : nullptr;
+  std::vector<double> lam;
+  eigh_top(c->stream, c->Ct, e, n, chi, c->evd, c->ws, c->Q, chi, Pref, lam);
+  if (update) {
+    CTM_HIP(hipMemcpyAsync(c->P, c->Q, (size_t)n * chi * sizeof(double), hipMemcpyDeviceToDevice,
+                           c->stream));
+    c->p_rows = n;
+  }
+}
+
+void projector(ctm_ctx* c, DType e, bool update) {
+  if (c->cfg.proj == CTM_PROJ_EVD) evd_projector(c, e, update);
+  else qr_projector(c, e, update);
+}
+
 void step_once(ctm_ctx* c) {
   hipStream_t s = c->stream;
   const DType e = c->prec;
@@ -248,7 +269,7 @@ void step_once(ctm_ctx* c) {
     launch_eye(s, c->Q, DType::F64, (int)n, (int)n, n);
   } else {
     xn = chi;
-    qr_projector(c, e, true);
+    projector(c, e, true);
   }
   stage_end(c, CTM_STAGE_PROJECTOR);
   stage_begin(c, CTM_STAGE_RENORM_C);
@@ -355,7 +376,7 @@ int do_energy(ctm_ctx* c, const double* h_host, double* e_host, double* rho_host
     launch_eye(s, c->Q, f, (int)n, (int)n, n);
   } else {
     xm = chi;
-    qr_projector(c, f, false);
+    projector(c, f, false);
   }
   double* Ct = (double*)c->Ct;
   double* Gm = (double*)c->Gm;
@@ -414,8 +435,9 @@ bool valid_cfg(const ctm_config* cfg, std::string& why) {
   if (cfg->d < 1 || cfg->D < 1 || cfg->chi < 1) return why = "d, D and chi must be >= 1", false;
   if ((int64_t)cfg->d * cfg->D * cfg->D * cfg->D > 16384) return why = "d*D^3 > 16384", false;
   if ((int64_t)cfg->chi * cfg->D * cfg->D > QR_MAX_ROWS) return why = "chi*D^2 > 32768", false;
-  if (cfg->proj != CTM_PROJ_QR)
-    return why = "only the QR projector (CTM_PROJ_QR) is implemented", false;
+  if (cfg->proj != CTM_PROJ_QR && cfg->proj != CTM_PROJ_EVD) return why = "bad projector", false;
+  if (cfg->proj == CTM_PROJ_EVD && (int64_t)cfg->chi * cfg->D * cfg->D > 8192)
+    return why = "the eigendecomposition projector needs chi*D^2 <= 8192", false;
   if (cfg->prec < CTM_PREC_FP64 || cfg->prec > CTM_PREC_BF16) return why = "bad precision", false;
   return true;
 }
@@ -454,6 +476,8 @@ void allocate(ctm_ctx* c) {
   c->V2 = c->allocd(nmax * chi);
   c->qr = qr_work_carve(c->stream, c->alloc(qr_work_bytes((int)nmax, (int)chi)), (int)nmax,
                         (int)chi);
+  if (c->cfg.proj == CTM_PROJ_EVD)
+    c->evd = evd_work_carve(c->alloc(evd_work_bytes((int)nmax, (int)chi)), (int)nmax, (int)chi);
   size_t wsb = std::max(gemm_scratch_bytes(DType::F64, (int)nmax, (int)chi),
                         gemm_scratch_bytes(DType::F64, (int)chi, (int)chi));
   c->ws.bytes = wsb;

@@ -2,11 +2,13 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <vector>
 
 #include "ctm.h"
 #include "ctm_kernels.h"
 #include "gemm.hpp"
 #include "qr.hpp"
+#include "evd.hpp"
 
 using namespace ctm;
 
@@ -82,6 +84,30 @@ extern "C" int ctm_qr(const double* M_dev, int n, int k, double* Q_dev, double* 
       CTM_LAUNCHED();
     }
     CTM_HIP(hipStreamSynchronize(s));
+    return CTM_OK;
+  } catch (const DeviceError& ex) {
+    set_global_error(ex.what());
+    return CTM_EDEVICE;
+  } catch (const std::exception& ex) {
+    set_global_error(ex.what());
+    return CTM_EINVAL;
+  }
+}
+
+extern "C" int ctm_eigh(const double* A_dev, int n, int k, const double* P_dev, double* U_dev,
+                        double* lam_host, void* stream) {
+  if (!A_dev || !U_dev || !lam_host || n < 1 || k < 1 || k > n || n > 8192) {
+    set_global_error("ctm_eigh: bad arguments");
+    return CTM_EINVAL;
+  }
+  try {
+    hipStream_t s = (hipStream_t)stream;
+    DevBuf w(evd_work_bytes(n, k)), ws(gemm_scratch_bytes(DType::F64, n, k));
+    EvdWork ew = evd_work_carve(w.p, n, k);
+    std::vector<double> lam;
+    eigh_top(s, A_dev, DType::F64, n, k, ew, Scratch{ws.p, gemm_scratch_bytes(DType::F64, n, k)},
+             U_dev, k, P_dev, lam);
+    for (int i = 0; i < k; ++i) lam_host[i] = lam[i];
     return CTM_OK;
   } catch (const DeviceError& ex) {
     set_global_error(ex.what());

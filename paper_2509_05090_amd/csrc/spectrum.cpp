@@ -10,6 +10,8 @@
 #include <algorithm>
 #include <cfloat>
 #include <cmath>
+#include <cstdint>
+#include <numeric>
 
 namespace ctm {
 
@@ -120,6 +122,135 @@ double spectrum_change(const std::vector<double>& s, const std::vector<double>& 
     c = std::max(c, std::fabs(a - b));
   }
   return c;
+}
+
+namespace {
+
+// Gershgorin interval of the tridiagonal matrix.
+void gershgorin(const std::vector<double>& d, const std::vector<double>& e, double& lo, double& hi) {
+  const int n = (int)d.size();
+  lo = hi = d[0];
+  for (int i = 0; i < n; ++i) {
+    const double r = (i > 0 ? std::fabs(e[i - 1]) : 0.0) + (i + 1 < n ? std::fabs(e[i]) : 0.0);
+    lo = std::min(lo, d[i] - r);
+    hi = std::max(hi, d[i] + r);
+  }
+}
+
+// Solve (T - lam I) y = b in place by Gaussian elimination with partial
+// pivoting on the tridiagonal (rows swap with their successor only); zero
+// pivots are replaced by a tiny multiple of the matrix scale.
+void tridiag_shifted_solve(const std::vector<double>& d, const std::vector<double>& e, double lam,
+                           double tiny, std::vector<double>& b) {
+  const int n = (int)d.size();
+  // row i of the current (possibly swapped) system: a[i] (diag), u1[i], u2[i] (fill-in)
+  std::vector<double> a(n), u1(n, 0.0), u2(n, 0.0), sub(n, 0.0);
+  for (int i = 0; i < n; ++i) a[i] = d[i] - lam;
+  for (int i = 0; i + 1 < n; ++i) {
+    u1[i] = e[i];
+    sub[i + 1] = e[i];
+  }
+  for (int i = 0; i + 1 < n; ++i) {
+    // eliminate sub[i+1] (entry (i+1, i)) using row i or swapped row i+1
+    if (std::fabs(sub[i + 1]) > std::fabs(a[i])) {
+      // swap rows i and i+1 (row i+1 has entries at i, i+1, i+2)
+      const double r0 = sub[i + 1], r1 = a[i + 1], r2 = i + 2 < n ? u1[i + 1] : 0.0;
+      const double s0 = a[i], s1 = u1[i], s2 = u2[i];
+      a[i] = r0;
+      u1[i] = r1;
+      u2[i] = r2;
+      std::swap(b[i], b[i + 1]);
+      const double m = s0 / r0;
+      a[i + 1] = s1 - m * r1;
+      if (i + 2 < n) u1[i + 1] = s2 - m * r2;
+      b[i + 1] -= m * b[i];
+    } else {
+      if (a[i] == 0.0) a[i] = tiny;
+      const double m = sub[i + 1] / a[i];
+      a[i + 1] -= m * u1[i];
+      if (i + 2 < n) u1[i + 1] -= m * u2[i];
+      b[i + 1] -= m * b[i];
+    }
+  }
+  if (a[n - 1] == 0.0) a[n - 1] = tiny;
+  for (int i = n - 1; i >= 0; --i) {
+    double t = b[i];
+    if (i + 1 < n) t -= u1[i] * b[i + 1];
+    if (i + 2 < n) t -= u2[i] * b[i + 2];
+    b[i] = t / (a[i] == 0.0 ? tiny : a[i]);
+  }
+}
+
+}  // namespace
+
+double tridiag_eigenvalue(const std::vector<double>& d, const std::vector<double>& e, int j) {
+  double lo, hi;
+  gershgorin(d, e, lo, hi);
+  const double scale = std::max(std::fabs(lo), std::fabs(hi));
+  double a = lo, b = hi;
+  for (int it = 0; it < 300; ++it) {
+    const double mid = 0.5 * (a + b);
+    if (b - a <= 2.0 * DBL_EPSILON * scale || mid == a || mid == b) break;
+    if (count_below(d, e, mid) > j)
+      b = mid;
+    else
+      a = mid;
+  }
+  return 0.5 * (a + b);
+}
+
+void tridiag_top_eigenpairs(const std::vector<double>& d, const std::vector<double>& e, int k,
+                            std::vector<double>& lam, std::vector<double>& z) {
+  const int n = (int)d.size();
+  // candidates: the k smallest and the k largest eigenvalues (by ascending index)
+  std::vector<int> idx;
+  for (int j = 0; j < std::min(k, n); ++j) idx.push_back(j);
+  for (int j = std::max(k, n - k); j < n; ++j) idx.push_back(j);
+  std::vector<double> val(idx.size());
+  for (size_t t = 0; t < idx.size(); ++t) val[t] = tridiag_eigenvalue(d, e, idx[t]);
+  std::vector<int> ord(idx.size());
+  std::iota(ord.begin(), ord.end(), 0);
+  std::sort(ord.begin(), ord.end(), [&](int p, int q) {
+    if (std::fabs(val[p]) != std::fabs(val[q])) return std::fabs(val[p]) > std::fabs(val[q]);
+    if (val[p] != val[q]) return val[p] > val[q];
+    return idx[p] < idx[q];
+  });
+  lam.resize(k);
+  for (int t = 0; t < k; ++t) lam[t] = val[ord[t]];
+  double lo, hi;
+  gershgorin(d, e, lo, hi);
+  const double tnorm = std::max(std::fabs(lo), std::fabs(hi));
+  const double tiny = DBL_EPSILON * std::max(tnorm, DBL_MIN);
+  const double cluster = 1e-3 * tnorm;
+  z.assign((size_t)n * k, 0.0);
+  std::vector<std::vector<double>> vecs;
+  uint64_t state = 0x9E3779B97F4A7C15ull;
+  for (int t = 0; t < k; ++t) {
+    std::vector<double> y(n);
+    for (int i = 0; i < n; ++i) {  // deterministic start vector (splitmix64 draws in (-1, 1))
+      state += 0x9E3779B97F4A7C15ull;
+      uint64_t v = state;
+      v = (v ^ (v >> 30)) * 0xBF58476D1CE4E5B9ull;
+      v = (v ^ (v >> 27)) * 0x94D049BB133111EBull;
+      v ^= v >> 31;
+      y[i] = (double)(v >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+    }
+    for (int it = 0; it < 4; ++it) {
+      tridiag_shifted_solve(d, e, lam[t], tiny, y);
+      for (int q = 0; q < t; ++q)
+        if (std::fabs(lam[q] - lam[t]) < cluster) {
+          double dot = 0.0;
+          for (int i = 0; i < n; ++i) dot += vecs[q][i] * y[i];
+          for (int i = 0; i < n; ++i) y[i] -= dot * vecs[q][i];
+        }
+      double nr = 0.0;
+      for (double v : y) nr += v * v;
+      nr = std::sqrt(nr);
+      for (double& v : y) v /= nr;
+    }
+    vecs.push_back(y);
+    for (int i = 0; i < n; ++i) z[(size_t)i * k + t] = y[i];
+  }
 }
 
 }  // namespace ctm

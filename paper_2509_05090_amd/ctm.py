@@ -32,7 +32,7 @@ DTYPE_CODE = {"float64": 0, "float32": 1, "bfloat16": 2}
 
 EXPORTS = ("ctm_symmetrize", "ctm_init", "ctm_step", "ctm_converge", "ctm_energy",
            "ctm_grad", "ctm_spectrum", "ctm_query", "ctm_get_env", "ctm_set_env", "ctm_set_precision",
-           "ctm_free", "ctm_last_error", "ctm_gemm", "ctm_qr", "ctm_profile",
+           "ctm_free", "ctm_last_error", "ctm_gemm", "ctm_qr", "ctm_eigh", "ctm_profile",
            "ctm_profile_read")
 STAGES = ("corner", "projector", "renorm_c", "renorm_t", "big_gemm")
 
@@ -71,6 +71,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "ctm_gemm": (i, [i, i, i, i, vp, i64, i, i64, i64, vp, i64, i, i64, i64,
                          vp, i64, i, i64, i64, i, i, d, d, i, vp]),
         "ctm_qr": (i, [vp, i, i, vp, vp, vp]),
+        "ctm_eigh": (i, [vp, i, i, vp, vp, pd, vp]),
         "ctm_profile": (i, [vp, i]),
         "ctm_profile_read": (i, [vp, pd, ctypes.POINTER(i64), pd]),
     }
@@ -136,6 +137,17 @@ def qr(M):
     R = torch.empty((k, k), dtype=torch.float64, device=M.device)
     _check(_lib.ctm_qr(_ptr(M.contiguous()), n, k, _ptr(Q), _ptr(R), _stream()))
     return Q, R
+
+
+def eigh_top(A, k, P=None):
+    """ctm_eigh on an (n, n) float64 GPU tensor: (U (n, k) tensor, eigenvalues)."""
+    import torch
+    n = A.shape[0]
+    U = torch.empty((n, k), dtype=torch.float64, device=A.device)
+    lam = np.zeros(k)
+    _check(_lib.ctm_eigh(_ptr(A.contiguous()), n, k, _ptr(None if P is None else P.contiguous()),
+                         _ptr(U), lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream()))
+    return U, lam
 
 
 class Context:

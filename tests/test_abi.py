@@ -49,7 +49,7 @@ def test_argument_errors_without_device_work():
     bad = ctm._Config(2, 0, 8, 0, 0)
     assert lib.ctm_init(ctypes.byref(h), ctypes.byref(bad), ctypes.c_void_p(8),
                         ctypes.c_void_p(8), None) == ctm.CTM_EINVAL
-    evd = ctm._Config(2, 2, 8, 1, 0)
+    evd = ctm._Config(2, 10, 100, 1, 0)  # eigendecomposition projector needs chi D^2 <= 8192
     assert lib.ctm_init(ctypes.byref(h), ctypes.byref(evd), ctypes.c_void_p(8),
                         ctypes.c_void_p(8), None) == ctm.CTM_EINVAL
     assert lib.ctm_symmetrize(None, None, 2, 2, None) == ctm.CTM_EINVAL
