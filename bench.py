@@ -3,19 +3,23 @@
 
 Workload: honeycomb iPEPS, d=2, D=6, chi=144 (enlarged corner 5184 x 5184),
 seeded C3v-symmetrized Gaussian site tensor A = sym(G0 + 1e-2 G1) (seeds
-1003, 1004), rotated spin-1/2 Heisenberg bond energy.  A step is one CTMRG
-iteration: enlarged corner, reduced corner, FP64 QR projector with its basis
-tied to the previous one, corner and edge renormalization.
+1003, 1004), start matrix seed 1010, rotated spin-1/2 Heisenberg energy.  A
+step is one CTMRG iteration: enlarged corner, reduced corner, FP64 QR
+projector with its basis tied to the previous one, corner and edge
+renormalization.
 
 The headline `value` is the mixed-precision rate (FP32 matrix-core
 contractions with FP32 accumulation; QR, basis, normalization and energy in
-FP64); FP64 and BF16 rates are reported beside it, with each mode's energy
-and corner-spectrum error against the CPU oracle's stored run of the same
-number of steps.  Timed steps are bracketed by stream synchronization and
-run with the inputs resident in HBM.  The roofline figure is for the
-(chi D^2) x chi x (chi D^2) matrix-core kernels, timed with HIP events on the
-library's stream.  The CPU baseline times the oracle itself on the host for
-a bounded sample of full-size steps.
+FP64); FP64 and BF16 rates are reported beside it.  For each mode the run is
+also converged to the workload tolerance and its energy and corner spectrum
+are compared with the CPU oracle's converged run (tests/golden/c3_qr.json).
+Timed steps are bracketed by stream synchronization, inputs resident in
+HBM.  The roofline figure is for the (chi D^2) x chi x (chi D^2) matrix-core
+products, timed with HIP events on the library's stream; their HBM traffic
+comes from the rocprofv3 counter summary in profiles/ when one was taken for
+the current kernel.  A gradient leg times the fixed-point adjoint on the
+D=4, chi=100 Kitaev-Heisenberg workload.  The CPU baseline times the oracle
+itself on the host for a bounded sample of full-size steps.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -24,6 +28,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -31,6 +36,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
+GEMM_KERNEL = {"fp64": "gemm_kernel<double", "fp32": "gemm_kernel<float", "bf16": "gemm_kernel<__bf16"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ctmrg_c3_big_gemm_traffic.md")
 
 
 def log(*a):
@@ -38,9 +45,9 @@ def log(*a):
 
 
 def gpu_rate(ctm, torch, A, G, chi, prec, warmup, steps, n_check=10):
-    """Steps/s of `steps` timed steps after `warmup` untimed ones; also the
-    rate with the corner-spectrum check every n_check steps, and the stage
-    profile of 10 further steps."""
+    """Steps/s of `steps` timed steps after `warmup` untimed ones (from the
+    truncated regime), also with the corner-spectrum check every n_check
+    steps, and the stage profile of 10 further steps."""
     with ctm.Context(A, G, chi, prec=prec) as c:
         c.step(max(warmup, 3))
         torch.cuda.synchronize()
@@ -63,18 +70,47 @@ def gpu_rate(ctm, torch, A, G, chi, prec, warmup, steps, n_check=10):
     return steps / dt, steps / dt_check, stages, flops
 
 
-def gpu_energy(ctm, torch, A, G, chi, prec, nsteps, h):
+def gpu_converged(ctm, torch, A, G, chi, prec, tol, max_steps, h):
+    """Converge (spectrum check every 10 steps); energy, spectrum, steps, time."""
     with ctm.Context(A, G, chi, prec=prec) as c:
-        c.step(nsteps)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        steps, delta, ok = c.converge(tol, max_steps, n_check=10)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
         e, _ = c.energy(h)
         s = c.spectrum()
-    return e, s
+    return e, s, steps, delta, ok, dt
+
+
+def gradient_leg(ctm, torch, ci):
+    """Fixed-point gradient on the D=4, chi=100 KH workload: converge, then
+    time ctm_grad."""
+    w = ci.WORKLOADS["c4"]
+    h = ci.site_energy_operator(w)
+    dev = torch.device("cuda:0")
+    A = ctm.symmetrize(torch.tensor(ci.raw_site_tensor(w), device=dev))
+    G = torch.tensor(ci.start_matrix(w), device=dev)
+    with ctm.Context(A, G, w.chi) as c:
+        t0 = time.perf_counter()
+        steps, delta, ok = c.converge(1e-14, 6000, n_check=20)
+        torch.cuda.synchronize()
+        t_conv = time.perf_counter() - t0
+        c.grad(h, mode=0, tol=1e-12)  # allocates the adjoint workspace
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        g, e, iters, gok = c.grad(h, mode=0, tol=1e-12)
+        torch.cuda.synchronize()
+        t_grad = time.perf_counter() - t1
+    return {"workload": "d=2 D=4 chi=100 Kitaev-Heisenberg phi=0.3pi, FP64",
+            "converge_steps": steps, "converge_s": t_conv, "adjoint_steps": iters,
+            "grad_ms": 1e3 * t_grad, "grad_converged": gok, "e_site": e,
+            "grad_norm": float(torch.linalg.norm(g).item())}
 
 
 def cpu_baseline(w, sample_steps):
     """The oracle on the host: `sample_steps` full-size steps after the two
     growth steps, reported as steps/s."""
-    import numpy as np
     from threadpoolctl import threadpool_info
 
     import ctm_inputs as ci
@@ -92,6 +128,29 @@ def cpu_baseline(w, sample_steps):
                       f"after the 2 growth steps; NumPy float64 with {threads} BLAS threads"}
 
 
+def stored_traffic(prec):
+    """HBM bytes per launch of the big products from the committed counter
+    summary, if it covers this kernel: a line `traffic_bytes_per_launch
+    <prec> <bytes>` in profiles/ctmrg_c3_big_gemm_traffic.md."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    for line in open(TRAFFIC_FILE):
+        m = re.match(r"\s*traffic_bytes_per_launch\s+(\w+)\s+([0-9.eE+]+)", line)
+        if m and m.group(1) == prec:
+            return float(m.group(2))
+    return None
+
+
+def copy_probe(torch):
+    """A plain 512 MiB device-to-device copy: the reference for scaling the
+    FETCH_SIZE / WRITE_SIZE counters."""
+    a = torch.ones(64 << 20, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,6 +158,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--cpu-sample", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-converge", action="store_true")
+    ap.add_argument("--no-grad", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--modes", default="fp32,fp64,bf16")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -113,6 +175,8 @@ def main():
     import ctm_inputs as ci
     from paper_2509_05090_amd import ctm
 
+    if args.copy_probe:
+        copy_probe(torch)
     w = ci.WORKLOADS["c3"]
     dev = torch.device("cuda:0")
     raw = torch.tensor(ci.raw_site_tensor(w), device=dev)
@@ -121,6 +185,7 @@ def main():
     h = ci.site_energy_operator(w)
     gold_path = os.path.join(ROOT, "tests", "golden", "c3_qr.json")
     gold = json.load(open(gold_path)) if os.path.exists(gold_path) else None
+    gold_ok = gold is not None and gold.get("last_delta", 1.0) < w.tol
 
     modes = args.modes.split(",")
     res = {}
@@ -134,26 +199,36 @@ def main():
         r["big_gemm"] = {"launches": big_n, "avg_ms": big_ms / max(big_n, 1),
                          "flops_per_launch": flops / max(big_n, 1),
                          "tflops": flops / (big_ms * 1e-3) / 1e12 if big_ms > 0 else None}
-        if gold is not None:
-            e, s = gpu_energy(ctm, torch, A, G, w.chi, prec, gold["steps"], h)
-            r["e_site"] = e
-            r["e_err_vs_oracle"] = abs(e - gold["e_site"])
-            so = np.array(gold["spectrum"])
-            m = min(len(s), len(so))
-            r["spectrum_err_vs_oracle"] = float(np.abs(s[:m] - so[:m]).max())
-            r["oracle_steps"] = gold["steps"]
+        if not args.no_converge:
+            tol = {"fp64": w.tol, "fp32": 1e-8, "bf16": 1e-4}[prec]
+            e, s, steps, delta, ok, dt = gpu_converged(ctm, torch, A, G, w.chi, prec, tol, 4000, h)
+            r.update({"e_site": e, "converge_tol": tol, "converge_steps": steps,
+                      "converge_delta": delta, "converged": ok, "converge_s": dt})
+            if gold_ok:
+                so = np.array(gold["spectrum"])
+                m = min(len(s), len(so))
+                r["e_err_vs_oracle"] = abs(e - gold["e_site"])
+                r["spectrum_err_vs_oracle"] = float(np.abs(s[:m] - so[:m]).max())
+                r["oracle_steps"] = gold["steps"]
         res[prec] = r
         log(f"[bench] {prec}: {json.dumps(r)}")
+
+    grad = None
+    if not args.no_grad:
+        log("[bench] gradient leg (D=4, chi=100)")
+        grad = gradient_leg(ctm, torch, ci)
+        log(f"[bench] gradient: {json.dumps(grad)}")
 
     head = "fp32" if "fp32" in res else modes[0]
     hr = res[head]
     bg = hr["big_gemm"]
     achieved = bg["tflops"]
+    traffic = stored_traffic(head)
     roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[head],
                 "unit": "TFLOP/s", "frac": (achieved / PEAK_TFLOPS[head]) if achieved else None,
-                "traffic": None,
-                "kernel": f"gemm_kernel<{head}> on the {w.n} x {w.chi} x {w.n} products "
-                          f"(W, M, Gm, V2 and the transposed T' product)",
+                "traffic": traffic,
+                "kernel": f"{GEMM_KERNEL[head]}, ...> on the {w.n} x {w.chi} x {w.n} products "
+                          f"(W = V TCp^T, M = Ct P, Ct Q, V Q and the transposed T' = Q^T V3)",
                 "avg_launch_ms": bg["avg_ms"], "flops_per_launch": bg["flops_per_launch"]}
     cpu = None
     if not args.no_cpu_baseline:
@@ -181,6 +256,7 @@ def main():
         "modes": res,
         "speedup_mixed_vs_fp64": (res["fp32"]["iters_per_s"] / res["fp64"]["iters_per_s"])
         if "fp32" in res and "fp64" in res else None,
+        "gradient": grad,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

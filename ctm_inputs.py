@@ -54,7 +54,7 @@ WORKLOADS = {
     "c1": Workload("c1", 2, 2, 16, 1001, 1008, model="heisenberg", steps=50),
     "c2": Workload("c2", 2, 4, 64, 1002, 1009, model="kitaev", tol=1e-12),
     "c3": Workload("c3", 2, 6, 144, 1003, 1010, seed_A2=1004, eps=1e-2,
-                   model="heisenberg", tol=1e-10),
+                   model="heisenberg", tol=1e-12),
     "c4": Workload("c4", 2, 4, 100, 1005, 1012, model="kh", tol=1e-12),
     "c5": Workload("c5", 2, 8, 256, 1006, 1013, model="heisenberg", tol=1e-8),
 }

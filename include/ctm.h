@@ -68,8 +68,16 @@ typedef enum { CTM_PROJ_QR = 0, CTM_PROJ_EVD = 1 } ctm_proj;
 /* Arithmetic of the contractions.  The QR, the sign gauge, the
  * normalization of C and T and the energy are FP64 in every mode; the master
  * copies of C, T and P are FP64.  FP32 and BF16 run the contractions on FP32
- * and BF16 matrix cores with FP32 accumulation. */
-typedef enum { CTM_PREC_FP64 = 0, CTM_PREC_FP32 = 1, CTM_PREC_BF16 = 2 } ctm_prec;
+ * and BF16 matrix cores with FP32 accumulation.  CTM_PREC_LADDER starts on
+ * BF16; ctm_converge moves it to FP32 when the spectrum change falls below
+ * 1e-4 (or stops improving) and to FP64 below 1e-9, and reports convergence
+ * only on the FP64 rung; ctm_step runs the current rung. */
+typedef enum {
+  CTM_PREC_FP64 = 0,
+  CTM_PREC_FP32 = 1,
+  CTM_PREC_BF16 = 2,
+  CTM_PREC_LADDER = 3
+} ctm_prec;
 
 typedef struct {
   int d;        /* physical dimension, >= 1 */
@@ -181,8 +189,9 @@ enum {
   CTM_STAGE_PROJECTOR = 1, /* reduced corner M = Ct P_prev, QR, basis (Fig. 3d) */
   CTM_STAGE_RENORM_C = 2,  /* C' = Q^T Ct Q, symmetrize, normalize (Fig. 3a) */
   CTM_STAGE_RENORM_T = 3,  /* T' = Q^T (T b) Q, normalize (Fig. 3b) */
-  CTM_STAGE_BIG_GEMM = 4,  /* the (chi_c D^2) x chi x (chi_c D^2) matrix-core kernels
-                              inside stages 0-3 (kernel time only) */
+  CTM_STAGE_BIG_GEMM = 4,  /* the three (chi_c D^2) x chi x (chi_c D^2) matrix-core
+                              products with untransposed operands inside stages 1-3,
+                              M = Ct P_prev, Ct Q, V Q (kernel time only) */
   CTM_NSTAGES = 5
 };
 

@@ -88,6 +88,7 @@ int guarded(ctm_ctx* c, F&& f) {
 }
 
 DType to_dtype(int prec) {
+  if (prec == CTM_PREC_LADDER) return DType::BF16;  // the ladder starts on BF16
   return prec == CTM_PREC_FP32 ? DType::F32 : (prec == CTM_PREC_BF16 ? DType::BF16 : DType::F64);
 }
 
@@ -176,9 +177,8 @@ void enlarged_corner(ctm_ctx* c, DType e) {
        Operand{aE, D2, false, 0, (int64_t)D2 * D2}, Output{c->V, D2, e, D2 * n, n}, x, D2, 1.0,
        0.0, c->ws);
   // 3. W = V TCp^T
-  KernelEvents ev;
   gemm(s, e, (int)n, x, (int)n, Operand{c->V, n, false}, Operand{c->TCp, n, true},
-       Output{c->W, x, e}, 1, 1, 1.0, 0.0, c->ws, 0, nullptr, big_gemm_events(c, ev, n, x, n));
+       Output{c->W, x, e}, 1, 1, 1.0, 0.0, c->ws);
   // 4. Ct[(alpha,k)][(beta,l)]
   gemm(s, e, x, D2, D2, Operand{c->W, x, true, (int64_t)D2 * x, 0},
        Operand{aE, (int64_t)D2 * D2, false, 0, D2}, Output{c->Ct, D2, e, D2 * n, n}, x, D2, 1.0,
@@ -274,7 +274,7 @@ void step_once(ctm_ctx* c) {
   stage_end(c, CTM_STAGE_PROJECTOR);
   stage_begin(c, CTM_STAGE_RENORM_C);
   const void* QE = as_prec(c, e, c->Q, c->QE, n * xn);
-  KernelEvents ev1, ev2, ev3;
+  KernelEvents ev1, ev2;
   // 6. Gm = Ct Q
   gemm(s, e, (int)n, xn, (int)n, Operand{c->Ct, n, false}, Operand{QE, xn, false},
        Output{c->Gm, xn, e}, 1, 1, 1.0, 0.0, c->ws, 0, nullptr,
@@ -297,8 +297,7 @@ void step_once(ctm_ctx* c) {
   // 10. T' = Q^T V3, normalized
   const int64_t tn = (int64_t)xn * D2 * xn;
   gemm(s, e, xn, D2 * xn, (int)n, Operand{QE, xn, true}, Operand{V3, (int64_t)D2 * xn, false},
-       Output{c->Tp, (int64_t)D2 * xn, DType::F64}, 1, 1, 1.0, 0.0, c->ws, 0, c->sumsq,
-       big_gemm_events(c, ev3, xn, (double)D2 * xn, n));
+       Output{c->Tp, (int64_t)D2 * xn, DType::F64}, 1, 1, 1.0, 0.0, c->ws, 0, c->sumsq);
   launch_scale_by_norm(s, c->Tp, c->Tn, tn, c->sumsq, sumsq_blocks(xn, D2 * xn), c->flag);
   stage_end(c, CTM_STAGE_RENORM_T);
   c->prof_active = false;
@@ -438,7 +437,7 @@ bool valid_cfg(const ctm_config* cfg, std::string& why) {
   if (cfg->proj != CTM_PROJ_QR && cfg->proj != CTM_PROJ_EVD) return why = "bad projector", false;
   if (cfg->proj == CTM_PROJ_EVD && (int64_t)cfg->chi * cfg->D * cfg->D > 8192)
     return why = "the eigendecomposition projector needs chi*D^2 <= 8192", false;
-  if (cfg->prec < CTM_PREC_FP64 || cfg->prec > CTM_PREC_BF16) return why = "bad precision", false;
+  if (cfg->prec < CTM_PREC_FP64 || cfg->prec > CTM_PREC_LADDER) return why = "bad precision", false;
   return true;
 }
 
@@ -586,11 +585,32 @@ int ctm_converge(ctm_ctx* c, double tol, int max_steps, int n_check, int* steps_
     int taken = 0;
     double delta = std::numeric_limits<double>::infinity();
     int rc = CTM_OK;
+    // Precision ladder: BF16, then FP32, then FP64; a rung is left when the
+    // spectrum change falls below its threshold or stops improving (the
+    // best change not halved in 8 checks).  Convergence counts on FP64 only.
+    const bool ladder = c->cfg.prec == CTM_PREC_LADDER;
+    double best = std::numeric_limits<double>::infinity();
+    int stale = 0;
     while (taken < max_steps) {
       const int k = std::min(n_check, max_steps - taken);
       rc = do_steps(c, k, &delta);
       taken += k;
       if (rc != CTM_OK) break;
+      if (ladder && c->prec != DType::F64) {
+        if (delta < 0.5 * best) {
+          best = delta;
+          stale = 0;
+        } else {
+          ++stale;
+        }
+        const double rung_tol = c->prec == DType::BF16 ? 1e-4 : 1e-9;
+        if (delta < rung_tol || stale >= 8) {
+          c->prec = c->prec == DType::BF16 ? DType::F32 : DType::F64;
+          best = std::numeric_limits<double>::infinity();
+          stale = 0;
+        }
+        continue;
+      }
       if (delta < tol) break;
     }
     if (steps_host) *steps_host = taken;
@@ -672,7 +692,7 @@ int ctm_set_env(ctm_ctx* c, int chi_c, const double* C_dev, const double* T_dev,
 
 int ctm_set_precision(ctm_ctx* c, int prec) {
   return guarded(c, [&]() -> int {
-    if (prec < CTM_PREC_FP64 || prec > CTM_PREC_BF16) throw std::invalid_argument("bad precision");
+    if (prec < CTM_PREC_FP64 || prec > CTM_PREC_LADDER) throw std::invalid_argument("bad precision");
     c->prec = to_dtype(prec);
     c->cfg.prec = prec;
     return CTM_OK;

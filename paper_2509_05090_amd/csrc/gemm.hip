@@ -250,13 +250,15 @@ namespace {
 struct TileCfg {
   int BM, BN;
 };
-constexpr TileCfg CFGS[3] = {{64, 64}, {64, 48}, {32, 32}};
+constexpr int NCFG = 4;
+constexpr TileCfg CFGS[NCFG] = {{64, 64}, {64, 48}, {48, 64}, {32, 32}};
 
 template <typename E, bool AT, bool BT, bool SPLIT>
 void launch_cfg(int cfg, dim3 grid, hipStream_t s, const GemmArgs& a) {
   switch (cfg) {
     case 0: gemm_kernel<E, AT, BT, 64, 64, 2, 2, SPLIT><<<grid, 256, 0, s>>>(a); break;
     case 1: gemm_kernel<E, AT, BT, 64, 48, 4, 1, SPLIT><<<grid, 256, 0, s>>>(a); break;
+    case 2: gemm_kernel<E, AT, BT, 48, 64, 1, 4, SPLIT><<<grid, 256, 0, s>>>(a); break;
     default: gemm_kernel<E, AT, BT, 32, 32, 2, 2, SPLIT><<<grid, 256, 0, s>>>(a); break;
   }
 }
@@ -295,11 +297,14 @@ void launch_reduce(DType out, const Acc* W, int S, int M, int N, void* C, int64_
   }
 }
 
+// Tile of least padded area; the 32x32 tile re-reads its operands twice as
+// often, so it is charged a third more area.
 int pick_cfg(int M, int N) {
   int best = 0;
   int64_t best_area = INT64_MAX;
-  for (int c = 0; c < 3; ++c) {
-    const int64_t area = cdiv(M, CFGS[c].BM) * CFGS[c].BM * cdiv(N, CFGS[c].BN) * CFGS[c].BN;
+  for (int c = 0; c < NCFG; ++c) {
+    int64_t area = cdiv(M, CFGS[c].BM) * CFGS[c].BM * cdiv(N, CFGS[c].BN) * CFGS[c].BN;
+    if (CFGS[c].BM * CFGS[c].BN < 64 * 48) area += area / 3;
     if (area < best_area) {
       best_area = area;
       best = c;

@@ -27,7 +27,7 @@ CTM_ENONFINITE = -6
 CTM_ESTATE = -7
 
 PROJ = {"qr": 0, "evd": 1}
-PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
+PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "ladder": 3}
 DTYPE_CODE = {"float64": 0, "float32": 1, "bfloat16": 2}
 
 EXPORTS = ("ctm_symmetrize", "ctm_init", "ctm_step", "ctm_converge", "ctm_energy",

@@ -159,3 +159,17 @@ def test_converge_reports_steps_and_delta():
     steps2, delta2, ok2 = c.converge(1e-30, 3, n_check=1)
     assert not ok2 and steps2 == 3
     c.close()
+
+
+def test_precision_ladder_reaches_fp64_energy():
+    """BF16 -> FP32 -> FP64 ladder on the D=4, chi=64 Kitaev workload: the
+    converged energy is the FP64 one."""
+    w = ci.WORKLOADS["c2"]
+    gold = _gold("c2_qr.json")
+    c, _ = gpu_context(w, prec="ladder")
+    steps, delta, ok = c.converge(w.tol, 4000, n_check=10)
+    e, _ = c.energy(ci.site_energy_operator(w))
+    c.close()
+    print(f"ladder: {steps} steps, |dE| = {abs(e - gold['e_site']):.3e}")
+    assert ok and delta < w.tol
+    assert abs(e - gold["e_site"]) < 1e-10
