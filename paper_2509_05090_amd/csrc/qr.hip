@@ -406,17 +406,26 @@ __global__ __launch_bounds__(AT) void qr_apply_kernel(double* __restrict__ B, in
   auto bat = [&](int r) -> double { return (r < rows && colok) ? B[grow(r) * ldb + col] : 0.0; };
   for (int i = tid; i < NBT * NBT; i += AT) Tsh[i / NBT][i % NBT] = T[i];
 
-  // W = Y^T B: wavefront wv takes the 4-row steps k0 = 4 (wv + AW s)
+  // W = Y^T B: wavefront wv takes the 4-row steps k0 = 4 (wv + AW s); the
+  // loads of a batch of steps are issued before its products.
   d4v acc[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = d4v{0.0, 0.0, 0.0, 0.0};
-#pragma unroll 2
-  for (int k0 = 4 * wv; k0 < rows; k0 += 4 * AW) {
-    const int r = k0 + grp;
-    const double b = bat(r);
+  constexpr int KB = 8;  // steps per batch
+  for (int k0 = 4 * wv; k0 < rows; k0 += 4 * AW * KB) {
+    double yb[KB][NT], bb[KB];
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
-      acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(yat(r, 16 * t + i16), b, acc[t], 0, 0, 0);
+    for (int it = 0; it < KB; ++it) {
+      const int r = k0 + 4 * AW * it + grp;
+      bb[it] = bat(r);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) yb[it][t] = yat(r, 16 * t + i16);
+    }
+#pragma unroll
+    for (int it = 0; it < KB; ++it)
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(yb[it][t], bb[it], acc[t], 0, 0, 0);
   }
   // result layout: register e of lane (grp, i16) holds row 4 e + grp, column i16
 #pragma unroll
@@ -432,15 +441,12 @@ __global__ __launch_bounds__(AT) void qr_apply_kernel(double* __restrict__ B, in
     W[q][j] = s;
   }
   __syncthreads();
-  // W <- op(T) W (T upper triangular)
+  // W <- op(T) W (T upper triangular, zeros below the diagonal)
   double w2 = 0.0;
   if (tid < NBT * ACW) {
     const int q = tid / ACW, j = tid % ACW;
-    if (TRANS) {
-      for (int p = 0; p <= q; ++p) w2 += Tsh[p][q] * W[p][j];
-    } else {
-      for (int p = q; p < NBT; ++p) w2 += Tsh[q][p] * W[p][j];
-    }
+#pragma unroll
+    for (int p = 0; p < NBT; ++p) w2 += (TRANS ? Tsh[p][q] : Tsh[q][p]) * W[p][j];
   }
   __syncthreads();
   if (tid < NBT * ACW) W[tid / ACW][tid % ACW] = w2;
@@ -450,17 +456,19 @@ __global__ __launch_bounds__(AT) void qr_apply_kernel(double* __restrict__ B, in
 #pragma unroll
   for (int s = 0; s < NBT / 4; ++s) wop[s] = W[4 * s + grp][i16];
   for (int r0 = 16 * wv; r0 < rows; r0 += 16 * AW) {
+    double ya[NBT / 4], bo[4];
+#pragma unroll
+    for (int s = 0; s < NBT / 4; ++s) ya[s] = yat(r0 + i16, 4 * s + grp);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) bo[e] = bat(r0 + 4 * e + grp);
     d4v acc3 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int s = 0; s < NBT / 4; ++s)
-      acc3 = __builtin_amdgcn_mfma_f64_16x16x4f64(yat(r0 + i16, 4 * s + grp), wop[s], acc3, 0, 0, 0);
+      acc3 = __builtin_amdgcn_mfma_f64_16x16x4f64(ya[s], wop[s], acc3, 0, 0, 0);
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int r = r0 + 4 * e + grp;
-      if (r < rows && colok) {
-        double* dst = B + grow(r) * ldb + col;
-        *dst = *dst - acc3[e];
-      }
+      if (r < rows && colok) B[grow(r) * ldb + col] = bo[e] - acc3[e];
     }
   }
 }
