@@ -255,20 +255,30 @@ __device__ __forceinline__ void local_qr(double (&a)[RPT][NBT], int m, int w, Qr
   for (int i = 0; i < NT; ++i)
 #pragma unroll
     for (int j = 0; j < NT; ++j) acc[i][j] = d4v{0.0, 0.0, 0.0, 0.0};
-#pragma unroll 2
-  for (int k0 = 4 * wid; k0 < m; k0 += 4 * QW) {
-    const int t = k0 + grp;
-    double y[NT];
+  // The loads of a batch of steps are all issued before its products (Y was
+  // just written, so each load is a full trip to the L2).
+  constexpr int KB = 8;
+  for (int kb = 4 * wid; kb < m; kb += 4 * QW * KB) {
+    double y[KB][NT];
 #pragma unroll
-    for (int i = 0; i < NT; ++i) {
-      const int q = 16 * i + i16;
-      y[i] = (t < m && q < w) ? Y[(int64_t)t * ldy + q] : 0.0;
+    for (int s = 0; s < KB; ++s) {
+      const int t = kb + 4 * QW * s + grp;
+#pragma unroll
+      for (int i = 0; i < NT; ++i) {
+        const int q = 16 * i + i16;
+        y[s][i] = (t < m && q < w) ? Y[(int64_t)t * ldy + q] : 0.0;
+      }
     }
 #pragma unroll
-    for (int i = 0; i < NT; ++i)
+    for (int s = 0; s < KB; ++s) {
+      if (kb + 4 * QW * s < m) {
 #pragma unroll
-      for (int j = i; j < NT; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(y[i], y[j], acc[i][j], 0, 0, 0);
+        for (int i = 0; i < NT; ++i)
+#pragma unroll
+          for (int j = i; j < NT; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(y[s][i], y[s][j], acc[i][j], 0, 0, 0);
+      }
+    }
   }
   // result layout: register e of lane (grp, i16) holds row 4 e + grp, column i16
 #pragma unroll
