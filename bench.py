@@ -18,8 +18,10 @@ HBM.  The roofline figure is for the (chi D^2) x chi x (chi D^2) matrix-core
 products, timed with HIP events on the library's stream; their HBM traffic
 comes from the rocprofv3 counter summary in profiles/ when one was taken for
 the current kernel.  A gradient leg times the fixed-point adjoint on the
-D=4, chi=100 Kitaev-Heisenberg workload.  The CPU baseline times the oracle
-itself on the host for a bounded sample of full-size steps.
+D=4, chi=100 Kitaev-Heisenberg workload, and a large leg reports FP32 and
+FP64 rates and the checkpointed gradient time at D=8, chi=256 (enlarged
+corner 16384 x 16384).  The CPU baseline times the oracle itself on the host
+for a bounded sample of full-size steps.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -151,6 +153,40 @@ def copy_probe(torch):
     torch.cuda.synchronize()
 
 
+def large_leg(ctm, torch, ci, steps, k_grad):
+    """D=8, chi=256 (enlarged corner 16384 x 16384): rate of FP32 and FP64
+    steps from the same start (after the two growth steps and one full-size
+    step), and the time of the checkpointed gradient through k_grad tracked
+    FP64 steps (the state is left unchanged by ctm_grad)."""
+    w = ci.WORKLOADS["c5"]
+    h = ci.site_energy_operator(w)
+    dev = torch.device("cuda:0")
+    A = ctm.symmetrize(torch.tensor(ci.raw_site_tensor(w), device=dev))
+    G = torch.tensor(ci.start_matrix(w), device=dev)
+    out = {"workload": "d=2 D=8 chi=256 (n = 16384), A seed 1006, start matrix seed 1013, "
+                       "rotated Heisenberg"}
+    for prec in ("fp32", "fp64"):
+        with ctm.Context(A, G, w.chi, prec=prec) as c:
+            c.step(3)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            c.step(steps)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            e, _ = c.energy(h)
+            out[prec] = {"iters_per_s": steps / dt, "steps": steps, "e_site_after": e}
+            if prec == "fp64" and k_grad > 0:
+                c.grad(h, mode=1, tol=0.0)  # allocates the adjoint workspace
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                g, _, _, _ = c.grad(h, mode=k_grad, tol=0.0)
+                torch.cuda.synchronize()
+                out["gradient"] = {"tracked_steps": k_grad, "grad_ms": 1e3 * (time.perf_counter() - t1),
+                                   "grad_norm": float(torch.linalg.norm(g).item()), "precision": "FP64"}
+    out["speedup_fp32_vs_fp64"] = out["fp32"]["iters_per_s"] / out["fp64"]["iters_per_s"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -162,6 +198,9 @@ def main():
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--modes", default="fp32,fp64,bf16")
+    ap.add_argument("--no-large", action="store_true", help="skip the D=8, chi=256 leg")
+    ap.add_argument("--large-steps", type=int, default=10)
+    ap.add_argument("--large-grad-k", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the CTMRG iteration is a sequential fixed-point map and "
@@ -219,6 +258,12 @@ def main():
         grad = gradient_leg(ctm, torch, ci)
         log(f"[bench] gradient: {json.dumps(grad)}")
 
+    large = None
+    if not args.no_large:
+        log("[bench] large leg (D=8, chi=256)")
+        large = large_leg(ctm, torch, ci, args.large_steps, args.large_grad_k)
+        log(f"[bench] large: {json.dumps(large)}")
+
     head = "fp32" if "fp32" in res else modes[0]
     hr = res[head]
     bg = hr["big_gemm"]
@@ -227,8 +272,8 @@ def main():
     roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[head],
                 "unit": "TFLOP/s", "frac": (achieved / PEAK_TFLOPS[head]) if achieved else None,
                 "traffic": traffic,
-                "kernel": f"{GEMM_KERNEL[head]}, ...> on the {w.n} x {w.chi} x {w.n} products "
-                          f"(W = V TCp^T, M = Ct P, Ct Q, V Q and the transposed T' = Q^T V3)",
+                "kernel": f"{GEMM_KERNEL[head]}, false, false, ...> on the three {w.n} x {w.chi} x {w.n} "
+                          f"products of a step with untransposed operands (M = Ct P, Ct Q, V Q)",
                 "avg_launch_ms": bg["avg_ms"], "flops_per_launch": bg["flops_per_launch"]}
     cpu = None
     if not args.no_cpu_baseline:
@@ -257,6 +302,7 @@ def main():
         "speedup_mixed_vs_fp64": (res["fp32"]["iters_per_s"] / res["fp64"]["iters_per_s"])
         if "fp32" in res and "fp64" in res else None,
         "gradient": grad,
+        "large": large,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -282,7 +282,7 @@ void step_once(ctm_ctx* c) {
   // 7. C' = Q^T Gm, symmetrized and normalized
   gemm(s, e, xn, xn, (int)n, Operand{QE, xn, true}, Operand{c->Gm, xn, false},
        Output{c->Cp, xn, DType::F64}, 1, 1, 1.0, 0.0, c->ws);
-  launch_corner_finalize(s, c->Cp, c->Cn, xn, c->flag);
+  launch_corner_finalize(s, c->Cp, c->Cn, xn, c->sumsq, c->flag);
   stage_end(c, CTM_STAGE_RENORM_C);
   stage_begin(c, CTM_STAGE_RENORM_T);
   // 8. V2 = V Q

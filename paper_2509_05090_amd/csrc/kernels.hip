@@ -158,39 +158,36 @@ __global__ void apply_signs_kernel(double* Q, int n, int k, const double* sgn, d
   }
 }
 
-__global__ __launch_bounds__(BT) void corner_finalize_kernel(const double* Cin, double* Cout,
-                                                             int k, int* flag) {
-  __shared__ double sh[BT / 64];
-  const int total = k * k;
+// Symmetrized corner (C + C^T)/2 and per-block sums of squares.
+__global__ __launch_bounds__(256) void sym_sumsq_kernel(const double* __restrict__ Cin,
+                                                       double* __restrict__ Cout, int k,
+                                                       double* __restrict__ parts) {
+  __shared__ double sh[4];
+  const int64_t total = (int64_t)k * k;
   double ss = 0.0;
-  for (int i = threadIdx.x; i < total; i += BT) {
-    const int r = i / k, c = i % k;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / k, c = i % k;
     const double v = 0.5 * (Cin[i] + Cin[c * k + r]);
+    Cout[i] = v;
     ss += v * v;
   }
-  const double nrm = sqrt(block_sum(ss, sh));
-  const bool bad = !(nrm > 0.0) || !isfinite(nrm);
-  const double inv = bad ? 0.0 : 1.0 / nrm;
-  for (int i = threadIdx.x; i < total; i += BT) {
-    const int r = i / k, c = i % k;
-    Cout[i] = 0.5 * (Cin[i] + Cin[c * k + r]) * inv;
-  }
-  if (threadIdx.x == 0 && bad) atomicOr(flag, 1);
+  ss = block_sum(ss, sh);
+  if (threadIdx.x == 0) parts[blockIdx.x] = ss;
 }
 
-__global__ void scale_by_norm_kernel(const double* in, double* out, int64_t n, const double* parts,
-                                     int nparts, int* flag) {
-  __shared__ double inv_sh;
-  if (threadIdx.x == 0) {
-    double t = 0.0;
-    for (int i = 0; i < nparts; ++i) t += parts[i];
-    const double nrm = sqrt(t);
-    const bool bad = !(nrm > 0.0) || !isfinite(nrm);
-    inv_sh = bad ? 0.0 : 1.0 / nrm;
-    if (bad && blockIdx.x == 0) atomicOr(flag, 1);
-  }
-  __syncthreads();
-  const double inv = inv_sh;
+// out = in / sqrt(sum of parts); every block sums the parts in the same
+// order.  Flags a zero or non-finite norm.
+__global__ __launch_bounds__(256) void scale_by_norm_kernel(const double* in, double* out,
+                                                           int64_t n, const double* parts,
+                                                           int nparts, int* flag) {
+  __shared__ double sh[4];
+  double t = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += blockDim.x) t += parts[i];
+  const double nrm = sqrt(block_sum(t, sh));
+  const bool bad = !(nrm > 0.0) || !isfinite(nrm);
+  const double inv = bad ? 0.0 : 1.0 / nrm;
+  if (bad && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(flag, 1);
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     out[i] = in[i] * inv;
@@ -297,8 +294,13 @@ void launch_apply_signs(hipStream_t s, double* Q, int n, int k, const double* sg
   CTM_LAUNCHED();
 }
 
-void launch_corner_finalize(hipStream_t s, const double* Cin, double* Cout, int k, int* flag) {
-  corner_finalize_kernel<<<1, BT, 0, s>>>(Cin, Cout, k, flag);
+void launch_corner_finalize(hipStream_t s, const double* Cin, double* Cout, int k, double* parts,
+                            int* flag) {
+  const int64_t total = (int64_t)k * k;
+  const int blocks = (int)std::min<int64_t>(CORNER_PARTS, std::max<int64_t>(1, (total + 1023) / 1024));
+  sym_sumsq_kernel<<<blocks, 256, 0, s>>>(Cin, Cout, k, parts);
+  CTM_LAUNCHED();
+  scale_by_norm_kernel<<<blocks, 256, 0, s>>>(Cout, Cout, total, parts, blocks, flag);
   CTM_LAUNCHED();
 }
 

@@ -27,7 +27,10 @@ void launch_diag_signs(hipStream_t s, const double* M, int ld, int k, double* sg
 // Q[:, j] *= sgn[j]; copy (nullable) = Q afterwards.
 void launch_apply_signs(hipStream_t s, double* Q, int n, int k, const double* sgn, double* copy);
 // Cout = sym(Cin) / ||sym(Cin)||_F (k x k); flag |= 1 if the norm is 0 or not finite.
-void launch_corner_finalize(hipStream_t s, const double* Cin, double* Cout, int k, int* flag);
+// parts: at least CORNER_PARTS doubles of scratch for the partial sums.
+constexpr int CORNER_PARTS = 256;
+void launch_corner_finalize(hipStream_t s, const double* Cin, double* Cout, int k, double* parts,
+                            int* flag);
 // out = in / sqrt(sum of nparts partial sums of squares); flag as above.
 void launch_scale_by_norm(hipStream_t s, const double* in, double* out, int64_t n,
                           const double* parts, int nparts, int* flag);
