@@ -130,16 +130,21 @@ def cpu_baseline(w, sample_steps):
                       f"after the 2 growth steps; NumPy float64 with {threads} BLAS threads"}
 
 
+# Tag of the current big-product kernel variant; a stored traffic figure is
+# used only if it was taken for this variant.
+KERNEL_TAG = "nt-vec16"
+
+
 def stored_traffic(prec):
     """HBM bytes per launch of the big products from the committed counter
     summary, if it covers this kernel: a line `traffic_bytes_per_launch
-    <prec> <bytes>` in profiles/ctmrg_c3_big_gemm_traffic.md."""
+    <prec> <kernel tag> <bytes>` in profiles/ctmrg_c3_big_gemm_traffic.md."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     for line in open(TRAFFIC_FILE):
-        m = re.match(r"\s*traffic_bytes_per_launch\s+(\w+)\s+([0-9.eE+]+)", line)
-        if m and m.group(1) == prec:
-            return float(m.group(2))
+        m = re.match(r"\s*traffic_bytes_per_launch\s+(\w+)\s+(\S+)\s+([0-9.eE+]+)", line)
+        if m and m.group(1) == prec and m.group(2) == KERNEL_TAG:
+            return float(m.group(3))
     return None
 
 
@@ -272,8 +277,9 @@ def main():
     roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[head],
                 "unit": "TFLOP/s", "frac": (achieved / PEAK_TFLOPS[head]) if achieved else None,
                 "traffic": traffic,
-                "kernel": f"{GEMM_KERNEL[head]}, false, false, ...> on the three {w.n} x {w.chi} x {w.n} "
-                          f"products of a step with untransposed operands (M = Ct P, Ct Q, V Q)",
+                "kernel": f"{GEMM_KERNEL[head]}, false, true, ...> on the three {w.n} x {w.chi} x {w.n} "
+                          f"products of a step (M = Ct P, Ct Q, V Q; the {w.chi}-wide operand "
+                          f"stored transposed)",
                 "avg_launch_ms": bg["avg_ms"], "flops_per_launch": bg["flops_per_launch"]}
     cpu = None
     if not args.no_cpu_baseline:

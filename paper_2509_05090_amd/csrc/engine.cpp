@@ -94,12 +94,6 @@ DType to_dtype(int prec) {
 
 // View of FP64 data in arithmetic e: the FP64 buffer itself for e = F64,
 // else a converted copy in `scratch`.
-const void* as_prec(ctm_ctx* c, DType e, const double* src, void* scratch, int64_t n) {
-  if (e == DType::F64) return src;
-  launch_cast(c->stream, src, scratch, e, n);
-  return scratch;
-}
-
 bool read_flag(ctm_ctx* c) {
   int f = 0;
   CTM_HIP(hipMemcpyAsync(&f, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
@@ -212,11 +206,13 @@ void qr_projector(ctm_ctx* c, DType e, bool update) {
       start_projector(c, n, Pref);
     }
   }
-  if (e != DType::F64 && Pref != c->P) throw std::logic_error("projector scratch clash");
-  const void* PE = as_prec(c, e, Pref, c->PE, (int64_t)n * chi);
+  // P_prev^T in the product's arithmetic (into W, which is free between the
+  // enlarged corner and the next step): both operands of the product below
+  // are then contiguous along its summed index.
+  launch_cast_transpose(s, Pref, c->W, e, n, chi);
   // 5. M = Ct P_prev (FP64 result), Q1 = thin QR factor
   KernelEvents ev;
-  gemm(s, e, n, chi, n, Operand{c->Ct, n, false}, Operand{PE, chi, false},
+  gemm(s, e, n, chi, n, Operand{c->Ct, n, false}, Operand{c->W, n, true},
        Output{c->M, chi, DType::F64}, 1, 1, 1.0, 0.0, c->ws, 0, nullptr,
        big_gemm_events(c, ev, n, chi, n));
   householder_qr(s, c->M, chi, n, chi, c->qr);
@@ -273,20 +269,23 @@ void step_once(ctm_ctx* c) {
   }
   stage_end(c, CTM_STAGE_PROJECTOR);
   stage_begin(c, CTM_STAGE_RENORM_C);
-  const void* QE = as_prec(c, e, c->Q, c->QE, n * xn);
+  // Q^T in the products' arithmetic (xn x n), contiguous along n for all four
+  // products that use it
+  void* QT = c->QE;
+  launch_cast_transpose(s, c->Q, QT, e, (int)n, xn);
   KernelEvents ev1, ev2;
   // 6. Gm = Ct Q
-  gemm(s, e, (int)n, xn, (int)n, Operand{c->Ct, n, false}, Operand{QE, xn, false},
+  gemm(s, e, (int)n, xn, (int)n, Operand{c->Ct, n, false}, Operand{QT, n, true},
        Output{c->Gm, xn, e}, 1, 1, 1.0, 0.0, c->ws, 0, nullptr,
        big_gemm_events(c, ev1, n, xn, n));
   // 7. C' = Q^T Gm, symmetrized and normalized
-  gemm(s, e, xn, xn, (int)n, Operand{QE, xn, true}, Operand{c->Gm, xn, false},
+  gemm(s, e, xn, xn, (int)n, Operand{QT, n, false}, Operand{c->Gm, xn, false},
        Output{c->Cp, xn, DType::F64}, 1, 1, 1.0, 0.0, c->ws);
   launch_corner_finalize(s, c->Cp, c->Cn, xn, c->sumsq, c->flag);
   stage_end(c, CTM_STAGE_RENORM_C);
   stage_begin(c, CTM_STAGE_RENORM_T);
   // 8. V2 = V Q
-  gemm(s, e, (int)n, xn, (int)n, Operand{c->V, n, false}, Operand{QE, xn, false},
+  gemm(s, e, (int)n, xn, (int)n, Operand{c->V, n, false}, Operand{QT, n, true},
        Output{c->V2, xn, e}, 1, 1, 1.0, 0.0, c->ws, 0, nullptr,
        big_gemm_events(c, ev2, n, xn, n));
   // 9. V3[alpha][(k,l)][nu] into the Ct buffer (Ct is no longer needed)
@@ -296,7 +295,7 @@ void step_once(ctm_ctx* c) {
        Output{V3, xn, e, (int64_t)D2 * D2 * xn}, x, 1, 1.0, 0.0, c->ws);
   // 10. T' = Q^T V3, normalized
   const int64_t tn = (int64_t)xn * D2 * xn;
-  gemm(s, e, xn, D2 * xn, (int)n, Operand{QE, xn, true}, Operand{V3, (int64_t)D2 * xn, false},
+  gemm(s, e, xn, D2 * xn, (int)n, Operand{QT, n, false}, Operand{V3, (int64_t)D2 * xn, false},
        Output{c->Tp, (int64_t)D2 * xn, DType::F64}, 1, 1, 1.0, 0.0, c->ws, 0, c->sumsq);
   launch_scale_by_norm(s, c->Tp, c->Tn, tn, c->sumsq, sumsq_blocks(xn, D2 * xn), c->flag);
   stage_end(c, CTM_STAGE_RENORM_T);

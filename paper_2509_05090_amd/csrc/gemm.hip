@@ -7,7 +7,11 @@
 // with 16 bytes of padding so that the 16-lane row reads of the MFMA operand
 // fetch hit distinct banks.  Within a chunk the four 16-lane groups of a
 // wavefront each own a contiguous quarter of the k range, so every lane
-// fetches its operand bytes with 16-byte LDS reads.
+// fetches its operand bytes with 16-byte LDS reads.  When an operand's rows
+// and batch offsets are 16-byte aligned it is fetched from memory with
+// 16-byte loads along its contiguous dimension (VEC); an operand contiguous
+// along k then lands in LDS with 16-byte stores, one contiguous along m or n
+// is scattered into the k-contiguous LDS rows.
 #include "gemm.hpp"
 
 namespace ctm {
@@ -79,7 +83,75 @@ __device__ inline int xcd_linear(int x, int nblk) {
   return xcd < rem ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
 }
 
-template <typename E, bool AT, bool BT, int BM, int BN, int WM, int WN, bool SPLIT>
+// Vectorized tile loader of one operand for a k-chunk: a ROWS x BK tile
+// (ROWS of the logical m or n index) whose memory layout is contiguous along
+// k (KC) or along the row index.  Vectors of V elements; every tile is
+// ROWS * BK / V vectors, spread over the 256 threads.
+template <typename E, int ROWS, int BK, bool KC>
+struct VecTile {
+  static constexpr int V = 16 / (int)sizeof(E);
+  static constexpr int NV = ROWS * BK / V;
+  static constexpr int PER = (NV + 255) / 256;
+  typedef E vec_t __attribute__((ext_vector_type(V)));
+  vec_t r[PER];
+  // p: operand base (batch applied); ld: leading dimension; r0: first row
+  // index of the tile; rlim: row count; k0, kend: k range of the chunk.
+  __device__ inline void load(const E* __restrict__ p, int64_t ld, int r0, int rlim, int k0,
+                              int kend) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int q = threadIdx.x + i * 256;
+      // KC: vector along k within row rr; else vector along rows at k row kk
+      const int rr = KC ? q / (BK / V) : (q % (ROWS / V)) * V;
+      const int kk = KC ? (q % (BK / V)) * V : q / (ROWS / V);
+      const int gr = r0 + rr, gk = k0 + kk;
+      vec_t v;
+#pragma unroll
+      for (int j = 0; j < V; ++j) v[j] = zero_of<E>();
+      if (q < NV) {
+        if (KC) {
+          if (gr < rlim) {
+            const E* src = p + (int64_t)gr * ld + gk;
+            if (gk + V <= kend) {
+              v = *(const vec_t*)src;
+            } else {
+#pragma unroll
+              for (int j = 0; j < V; ++j)
+                if (gk + j < kend) v[j] = src[j];
+            }
+          }
+        } else if (gk < kend) {
+          const E* src = p + (int64_t)gk * ld + gr;
+          if (gr + V <= rlim) {
+            v = *(const vec_t*)src;
+          } else {
+#pragma unroll
+            for (int j = 0; j < V; ++j)
+              if (gr + j < rlim) v[j] = src[j];
+          }
+        }
+      }
+      r[i] = v;
+    }
+  }
+  // LDS rows of LDK elements, k contiguous.
+  __device__ inline void store(E* __restrict__ lds, int LDK) const {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int q = threadIdx.x + i * 256;
+      if (q >= NV) continue;
+      if (KC) {
+        *(vec_t*)&lds[(q / (BK / V)) * LDK + (q % (BK / V)) * V] = r[i];
+      } else {
+        const int rr = (q % (ROWS / V)) * V, kk = q / (ROWS / V);
+#pragma unroll
+        for (int j = 0; j < V; ++j) lds[(rr + j) * LDK + kk] = r[i][j];
+      }
+    }
+  }
+};
+
+template <typename E, bool AT, bool BT, int BM, int BN, int WM, int WN, bool SPLIT, bool VEC>
 __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   using MF = Mfma<E>;
   using acc_t = typename MF::acc_t;
@@ -110,40 +182,52 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   const int nk = kend > kbeg ? (int)cdiv(kend - kbeg, BK) : 0;
 
   E ra[EA], rb[EB];
+  VecTile<E, BM, BK, !AT> va;
+  VecTile<E, BN, BK, BT> vb;
   auto load = [&](int k0) {
+    if constexpr (VEC) {
+      va.load(A, g.lda, m0, g.M, k0, kend);
+      vb.load(B, g.ldb, n0, g.N, k0, kend);
+    } else {
 #pragma unroll
-    for (int i = 0; i < EA; ++i) {
-      const int e = threadIdx.x + i * NT;
-      const int mm = AT ? e % BM : e / BK, kk = AT ? e / BM : e % BK;
-      const int gm = m0 + mm, gk = k0 + kk;
-      E v = zero_of<E>();
-      if (gm < g.M && gk < kend)
-        v = AT ? A[(int64_t)gk * g.lda + gm] : A[(int64_t)gm * g.lda + gk];
-      ra[i] = v;
-    }
+      for (int i = 0; i < EA; ++i) {
+        const int e = threadIdx.x + i * NT;
+        const int mm = AT ? e % BM : e / BK, kk = AT ? e / BM : e % BK;
+        const int gm = m0 + mm, gk = k0 + kk;
+        E v = zero_of<E>();
+        if (gm < g.M && gk < kend)
+          v = AT ? A[(int64_t)gk * g.lda + gm] : A[(int64_t)gm * g.lda + gk];
+        ra[i] = v;
+      }
 #pragma unroll
-    for (int i = 0; i < EB; ++i) {
-      const int e = threadIdx.x + i * NT;
-      const int nn = BT ? e / BK : e % BN, kk = BT ? e % BK : e / BN;
-      const int gn = n0 + nn, gk = k0 + kk;
-      E v = zero_of<E>();
-      if (gn < g.N && gk < kend)
-        v = BT ? B[(int64_t)gn * g.ldb + gk] : B[(int64_t)gk * g.ldb + gn];
-      rb[i] = v;
+      for (int i = 0; i < EB; ++i) {
+        const int e = threadIdx.x + i * NT;
+        const int nn = BT ? e / BK : e % BN, kk = BT ? e % BK : e / BN;
+        const int gn = n0 + nn, gk = k0 + kk;
+        E v = zero_of<E>();
+        if (gn < g.N && gk < kend)
+          v = BT ? B[(int64_t)gn * g.ldb + gk] : B[(int64_t)gk * g.ldb + gn];
+        rb[i] = v;
+      }
     }
   };
   auto store = [&](int buf) {
+    if constexpr (VEC) {
+      va.store(As[buf], LDK);
+      vb.store(Bs[buf], LDK);
+    } else {
 #pragma unroll
-    for (int i = 0; i < EA; ++i) {
-      const int e = threadIdx.x + i * NT;
-      const int mm = AT ? e % BM : e / BK, kk = AT ? e / BM : e % BK;
-      As[buf][mm * LDK + kk] = ra[i];
-    }
+      for (int i = 0; i < EA; ++i) {
+        const int e = threadIdx.x + i * NT;
+        const int mm = AT ? e % BM : e / BK, kk = AT ? e / BM : e % BK;
+        As[buf][mm * LDK + kk] = ra[i];
+      }
 #pragma unroll
-    for (int i = 0; i < EB; ++i) {
-      const int e = threadIdx.x + i * NT;
-      const int nn = BT ? e / BK : e % BN, kk = BT ? e % BK : e / BN;
-      Bs[buf][nn * LDK + kk] = rb[i];
+      for (int i = 0; i < EB; ++i) {
+        const int e = threadIdx.x + i * NT;
+        const int nn = BT ? e / BK : e % BN, kk = BT ? e % BK : e / BN;
+        Bs[buf][nn * LDK + kk] = rb[i];
+      }
     }
   };
 
@@ -253,28 +337,42 @@ struct TileCfg {
 constexpr int NCFG = 4;
 constexpr TileCfg CFGS[NCFG] = {{64, 64}, {64, 48}, {48, 64}, {32, 32}};
 
-template <typename E, bool AT, bool BT, bool SPLIT>
+template <typename E, bool AT, bool BT, bool SPLIT, bool VEC>
 void launch_cfg(int cfg, dim3 grid, hipStream_t s, const GemmArgs& a) {
   switch (cfg) {
-    case 0: gemm_kernel<E, AT, BT, 64, 64, 2, 2, SPLIT><<<grid, 256, 0, s>>>(a); break;
-    case 1: gemm_kernel<E, AT, BT, 64, 48, 4, 1, SPLIT><<<grid, 256, 0, s>>>(a); break;
-    case 2: gemm_kernel<E, AT, BT, 48, 64, 1, 4, SPLIT><<<grid, 256, 0, s>>>(a); break;
-    default: gemm_kernel<E, AT, BT, 32, 32, 2, 2, SPLIT><<<grid, 256, 0, s>>>(a); break;
+    case 0: gemm_kernel<E, AT, BT, 64, 64, 2, 2, SPLIT, VEC><<<grid, 256, 0, s>>>(a); break;
+    case 1: gemm_kernel<E, AT, BT, 64, 48, 4, 1, SPLIT, VEC><<<grid, 256, 0, s>>>(a); break;
+    case 2: gemm_kernel<E, AT, BT, 48, 64, 1, 4, SPLIT, VEC><<<grid, 256, 0, s>>>(a); break;
+    default: gemm_kernel<E, AT, BT, 32, 32, 2, 2, SPLIT, VEC><<<grid, 256, 0, s>>>(a); break;
   }
 }
 
-template <typename E, bool SPLIT>
+template <typename E, bool SPLIT, bool VEC>
 void launch_trans(bool at, bool bt, int cfg, dim3 grid, hipStream_t s, const GemmArgs& a) {
-  if (!at && !bt) launch_cfg<E, false, false, SPLIT>(cfg, grid, s, a);
-  else if (!at && bt) launch_cfg<E, false, true, SPLIT>(cfg, grid, s, a);
-  else if (at && !bt) launch_cfg<E, true, false, SPLIT>(cfg, grid, s, a);
-  else launch_cfg<E, true, true, SPLIT>(cfg, grid, s, a);
+  if (!at && !bt) launch_cfg<E, false, false, SPLIT, VEC>(cfg, grid, s, a);
+  else if (!at && bt) launch_cfg<E, false, true, SPLIT, VEC>(cfg, grid, s, a);
+  else if (at && !bt) launch_cfg<E, true, false, SPLIT, VEC>(cfg, grid, s, a);
+  else launch_cfg<E, true, true, SPLIT, VEC>(cfg, grid, s, a);
 }
 
 template <typename E>
-void launch_any(bool split, bool at, bool bt, int cfg, dim3 grid, hipStream_t s, const GemmArgs& a) {
-  if (split) launch_trans<E, true>(at, bt, cfg, grid, s, a);
-  else launch_trans<E, false>(at, bt, cfg, grid, s, a);
+void launch_any(bool split, bool vec, bool at, bool bt, int cfg, dim3 grid, hipStream_t s,
+                const GemmArgs& a) {
+  if (split) {
+    if (vec) launch_trans<E, true, true>(at, bt, cfg, grid, s, a);
+    else launch_trans<E, true, false>(at, bt, cfg, grid, s, a);
+  } else {
+    if (vec) launch_trans<E, false, true>(at, bt, cfg, grid, s, a);
+    else launch_trans<E, false, false>(at, bt, cfg, grid, s, a);
+  }
+}
+
+// 16-byte loads are legal for an operand whose base, leading dimension and
+// batch offsets are multiples of 16 bytes (tile origins along the
+// contiguous dimension are multiples of 16 bytes by construction).
+bool vec_ok(const Operand& o, size_t es) {
+  const int64_t v = 16 / (int64_t)es;
+  return ((uintptr_t)o.p % 16) == 0 && o.ld % v == 0 && o.s0 % v == 0 && o.s1 % v == 0;
 }
 
 template <typename Acc>
@@ -377,10 +475,11 @@ void gemm(hipStream_t s, DType e, int M, int N, int K, const Operand& A, const O
   }
   dim3 grid((unsigned)(tiles * nbatch), split ? ksplit : 1);
   if (ev) CTM_HIP(hipEventRecord(ev->begin, s));
+  const bool vec = vec_ok(A, dtype_size(e)) && vec_ok(B, dtype_size(e));
   switch (e) {
-    case DType::F64: launch_any<double>(split, A.trans, B.trans, cfg, grid, s, a); break;
-    case DType::F32: launch_any<float>(split, A.trans, B.trans, cfg, grid, s, a); break;
-    case DType::BF16: launch_any<bf16>(split, A.trans, B.trans, cfg, grid, s, a); break;
+    case DType::F64: launch_any<double>(split, vec, A.trans, B.trans, cfg, grid, s, a); break;
+    case DType::F32: launch_any<float>(split, vec, A.trans, B.trans, cfg, grid, s, a); break;
+    case DType::BF16: launch_any<bf16>(split, vec, A.trans, B.trans, cfg, grid, s, a); break;
   }
   CTM_LAUNCHED();
   if (ev) CTM_HIP(hipEventRecord(ev->end, s));

@@ -133,6 +133,28 @@ __global__ void cast_kernel(const double* __restrict__ src, T* __restrict__ dst,
     dst[i] = from_f64<T>(src[i]);
 }
 
+// dst (cols x rows, ld rows) = (T) src^T (src rows x cols, ld cols), through
+// 32 x 32 LDS tiles so that both sides are coalesced.
+template <typename T>
+__global__ __launch_bounds__(256) void cast_transpose_kernel(const double* __restrict__ src,
+                                                            T* __restrict__ dst, int rows,
+                                                            int cols) {
+  __shared__ double tile[32][33];
+  const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+#pragma unroll
+  for (int k = 0; k < 32; k += 8) {
+    const int r = r0 + ty + k, c = c0 + tx;
+    if (r < rows && c < cols) tile[ty + k][tx] = src[(int64_t)r * cols + c];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 32; k += 8) {
+    const int c = c0 + ty + k, r = r0 + tx;
+    if (r < rows && c < cols) dst[(int64_t)c * rows + r] = from_f64<T>(tile[tx][ty + k]);
+  }
+}
+
 template <typename T>
 __global__ void eye_kernel(T* Q, int n, int k, int64_t ld) {
   const int64_t total = (int64_t)n * k;
@@ -270,6 +292,24 @@ void launch_cast(hipStream_t s, const double* src, void* dst, DType t, int64_t n
       return;
     case DType::F32: cast_kernel<float><<<grid_for(n), 256, 0, s>>>(src, (float*)dst, n); break;
     case DType::BF16: cast_kernel<bf16><<<grid_for(n), 256, 0, s>>>(src, (bf16*)dst, n); break;
+  }
+  CTM_LAUNCHED();
+}
+
+void launch_cast_transpose(hipStream_t s, const double* src, void* dst, DType t, int rows,
+                           int cols) {
+  if (rows <= 0 || cols <= 0) return;
+  const dim3 grid((unsigned)cdiv(cols, 32), (unsigned)cdiv(rows, 32));
+  switch (t) {
+    case DType::F64:
+      cast_transpose_kernel<double><<<grid, 256, 0, s>>>(src, (double*)dst, rows, cols);
+      break;
+    case DType::F32:
+      cast_transpose_kernel<float><<<grid, 256, 0, s>>>(src, (float*)dst, rows, cols);
+      break;
+    case DType::BF16:
+      cast_transpose_kernel<bf16><<<grid, 256, 0, s>>>(src, (bf16*)dst, rows, cols);
+      break;
   }
   CTM_LAUNCHED();
 }

@@ -20,6 +20,10 @@ void launch_double_layer_open(hipStream_t s, const double* A, int d, int D, int 
 void launch_init_env(hipStream_t s, int D, double* C, double* T);
 // dst[i] = (T)src[i].
 void launch_cast(hipStream_t s, const double* src, void* dst, DType t, int64_t n);
+// dst (cols x rows, leading dimension rows) = (T) transpose of src (rows x
+// cols, leading dimension cols).
+void launch_cast_transpose(hipStream_t s, const double* src, void* dst, DType t, int rows,
+                           int cols);
 // Q = first k columns of the n x n identity, in type t, leading dimension ld.
 void launch_eye(hipStream_t s, void* Q, DType t, int n, int k, int64_t ld);
 // sgn[j] = -1 if M[j][j] < 0 else +1.

@@ -65,6 +65,35 @@ def test_gemm_split_k_fp64_output(prec):
     assert err < TOL[prec] * 10, err
 
 
+@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("ta,tb", [(False, False), (False, True), (True, False), (True, True)])
+@pytest.mark.parametrize("M,N,K,ksplit", [(136, 40, 264, 0), (134, 45, 261, 0), (70, 150, 1029, 3),
+                                          (200, 144, 5000, 0)])
+def test_gemm_aligned_operands(prec, ta, tb, M, N, K, ksplit):
+    """Leading dimensions padded to multiples of 16 bytes, so the 16-byte
+    load path runs, with ragged tiles and partial vectors at the k and m/n
+    ends (K, M, N not multiples of the vector width)."""
+    r = _rng(M * 31 + N * 7 + K + prec * 101 + 4 * ta + 2 * tb + ksplit)
+    pad = lambda x: (x + 7) // 8 * 8
+    ra, ca = (K, M) if ta else (M, K)
+    rb, cb = (N, K) if tb else (K, N)
+    A = r.standard_normal((ra, pad(ca)))
+    B = r.standard_normal((rb, pad(cb)))
+    Ad = torch.tensor(A, device=DEV).to(TDT[prec])
+    Bd = torch.tensor(B, device=DEV).to(TDT[prec])
+    Cd = torch.zeros((M, N), device=DEV, dtype=torch.float64)
+    ctm.gemm(Ad, Bd, Cd, M, N, K, lda=pad(ca), ldb=pad(cb), ldc=N, transA=ta, transB=tb,
+             prec=prec, ksplit=ksplit)
+    torch.cuda.synchronize()
+    Ah, Bh = _stored(A, prec)[:, :ca], _stored(B, prec)[:, :cb]
+    opA = Ah.T if ta else Ah
+    opB = Bh.T if tb else Bh
+    ref = opA @ opB
+    scale = np.abs(opA) @ np.abs(opB) + 1e-300
+    err = (np.abs(Cd.cpu().numpy() - ref) / scale).max()
+    assert err < TOL[prec] * 10, err
+
+
 def test_gemm_alpha_beta_in_place():
     err = run_gemm(200, 100, 16, 0, False, False, 13, ksplit=1, alpha=-1.0, beta=1.0)
     assert err < 1e-14
