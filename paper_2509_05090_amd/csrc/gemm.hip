@@ -413,6 +413,208 @@ int pick_cfg(int M, int N) {
 
 }  // namespace
 
+// Batches of small products (the pair contractions of the enlarged corner:
+// chi D^2 batches of chi x D^2 x D^2): C[b0,b1] = A[b0] B[b1] with K, N <= 64
+// and A independent of b1.  A workgroup holds a row tile of A[b0] in LDS
+// ([m][k], k contiguous) and runs over a group of b1: it stages B[b1] in LDS
+// ([n][k]) and its four wavefronts each take 16-row tiles of the output,
+// all 16-column tiles of a row tile at once, over the whole (short) k
+// range.  Each output element is written once, straight from the
+// accumulators.
+constexpr int SB_KMAX = 64, SB_NMAX = 64;
+constexpr int SB_LDS = 64 * 1024;
+
+struct SmallBatchArgs {
+  int M, N, K;
+  const void* A;
+  int64_t lda, sA0;
+  bool at;
+  const void* B;
+  int64_t ldb, sB1;
+  bool bt;
+  void* C;
+  int64_t ldc, sC0, sC1;
+  int nb0, nb1;
+  int mt;      // rows of A per workgroup (multiple of 16)
+  int mtiles;  // row tiles per b0
+  int group;   // b1 values per workgroup
+  int kp;      // LDS row length (elements)
+};
+
+template <typename E, int KS, int NT>
+__global__ __launch_bounds__(256) void small_batch_kernel(SmallBatchArgs g) {
+  using MF = Mfma<E>;
+  using accv = typename MF::accv;
+  constexpr int KSTEP = 4 * MF::KPL;  // k per MFMA
+  constexpr int KPAD = KS * KSTEP;    // k range held in LDS (zero beyond K)
+  constexpr int NP = NT * 16;         // columns held in LDS (zero beyond N)
+  extern __shared__ __attribute__((aligned(16))) unsigned char sb_lds[];
+  E* As = (E*)sb_lds;                 // [mt][kp]
+  E* Bs = As + (int64_t)g.mt * g.kp;  // [NP][kp]
+
+  const int b0 = blockIdx.x / g.mtiles, m0 = (blockIdx.x % g.mtiles) * g.mt;
+  const int rows = min(g.mt, g.M - m0);
+  const E* __restrict__ A = (const E*)g.A + (int64_t)b0 * g.sA0;
+
+  // A tile [m][k], zero beyond the data; loads issued in batches of LB per
+  // thread before their LDS stores.
+  constexpr int LB = 16;
+  const int atotal = g.mt * KPAD;
+  for (int base = 0; base < atotal; base += 256 * LB) {
+    E v[LB];
+#pragma unroll
+    for (int j = 0; j < LB; ++j) {
+      const int i = base + j * 256 + threadIdx.x;
+      const int m = g.at ? i % g.mt : i / KPAD, k = g.at ? i / g.mt : i % KPAD;
+      v[j] = zero_of<E>();
+      if (i < atotal && m < rows && k < g.K)
+        v[j] = g.at ? A[(int64_t)k * g.lda + m0 + m] : A[(int64_t)(m0 + m) * g.lda + k];
+    }
+#pragma unroll
+    for (int j = 0; j < LB; ++j) {
+      const int i = base + j * 256 + threadIdx.x;
+      const int m = g.at ? i % g.mt : i / KPAD, k = g.at ? i / g.mt : i % KPAD;
+      if (i < atotal) As[m * g.kp + k] = v[j];
+    }
+  }
+
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int r16 = lane & 15, grp = lane >> 4;
+  const int b1beg = blockIdx.y * g.group, b1end = min(g.nb1, b1beg + g.group);
+  // B[b1] as [n][k], held in registers one batch ahead of its use
+  constexpr int BPT = (NP * KPAD + 255) / 256;
+  E rb[BPT];
+  auto load_b = [&](int b1) {
+    const E* __restrict__ B = (const E*)g.B + (int64_t)b1 * g.sB1;
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) {
+      const int i = j * 256 + threadIdx.x;
+      const int n = g.bt ? i / KPAD : i % NP, k = g.bt ? i % KPAD : i / NP;
+      rb[j] = zero_of<E>();
+      if (i < NP * KPAD && n < g.N && k < g.K)
+        rb[j] = g.bt ? B[(int64_t)n * g.ldb + k] : B[(int64_t)k * g.ldb + n];
+    }
+  };
+  if (b1beg < b1end) load_b(b1beg);
+  for (int b1 = b1beg; b1 < b1end; ++b1) {
+    __syncthreads();  // previous B no longer read (and A stored, first time)
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) {
+      const int i = j * 256 + threadIdx.x;
+      const int n = g.bt ? i / KPAD : i % NP, k = g.bt ? i % KPAD : i / NP;
+      if (i < NP * KPAD) Bs[n * g.kp + k] = rb[j];
+    }
+    __syncthreads();
+    if (b1 + 1 < b1end) load_b(b1 + 1);
+    // B fragments of this batch, shared by all row tiles of the wavefront
+    E bf[NT][KS][MF::KPL];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int s = 0; s < KS; ++s)
+        __builtin_memcpy(&bf[t][s][0], &Bs[(t * 16 + r16) * g.kp + s * KSTEP + grp * MF::KPL],
+                         MF::KPL * sizeof(E));
+    E* __restrict__ C = (E*)g.C + (int64_t)b0 * g.sC0 + (int64_t)b1 * g.sC1;
+    for (int tm = wid; tm * 16 < rows; tm += 4) {
+      E af[KS][MF::KPL];
+#pragma unroll
+      for (int s = 0; s < KS; ++s)
+        __builtin_memcpy(&af[s][0], &As[(tm * 16 + r16) * g.kp + s * KSTEP + grp * MF::KPL],
+                         MF::KPL * sizeof(E));
+      accv acc[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[t] = accv{0, 0, 0, 0};
+#pragma unroll
+      for (int s = 0; s < KS; ++s)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] = MF::mma(&af[s][0], &bf[t][s][0], acc[t]);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int rr = MF::ROWS_INTERLEAVED ? r * 4 + grp : grp * 4 + r;
+          const int row = tm * 16 + rr, col = t * 16 + r16;
+          if (row < rows && col < g.N)
+            C[(int64_t)(m0 + row) * g.ldc + col] = from_f64<E>((double)acc[t][r]);
+        }
+      }
+    }
+  }
+}
+
+namespace {
+
+// Launches the small-batch kernel if the product has its shape; false if
+// not (the caller then uses the general kernel).
+bool small_batch(hipStream_t s, DType e, int M, int N, int K, const Operand& A, const Operand& B,
+                 const Output& C, int nb0, int nb1, double alpha, double beta) {
+  if (nb0 * (int64_t)nb1 <= 1 || K > SB_KMAX || N > SB_NMAX || A.s1 != 0 || B.s0 != 0 ||
+      alpha != 1.0 || beta != 0.0 || C.t != e)
+    return false;
+  const int es = (int)dtype_size(e);
+  const int kstep = e == DType::BF16 ? 32 : 4;
+  // instances: k steps x column tiles, the smallest that covers (K, N)
+  int ks = (int)cdiv(std::max(K, 1), kstep), nt = (int)cdiv(N, 16);
+  if (e == DType::BF16) {
+    ks = 2;
+    nt = nt <= 1 ? 1 : 4;
+  } else if (ks <= 1 && nt <= 1) {
+    ks = 1;
+    nt = 1;
+  } else if (ks <= 4 && nt <= 1) {
+    ks = 4;
+    nt = 1;
+  } else if (ks <= 9 && nt <= 3) {
+    ks = 9;
+    nt = 3;
+  } else {
+    ks = 16;
+    nt = 4;
+  }
+  const int kpad = ks * kstep;
+  const int kp = kpad + 16 / es;  // 16 bytes of row padding
+  const int np = nt * 16;
+  const int64_t bbytes = (int64_t)np * kp * es;
+  const int64_t mt_fit = (SB_LDS - bbytes) / ((int64_t)kp * es) / 16 * 16;
+  if (mt_fit < 16) return false;
+  SmallBatchArgs g{};
+  g.mt = (int)std::min<int64_t>(mt_fit, cdiv(M, 16) * 16);
+  g.mtiles = (int)cdiv(M, g.mt);
+  g.M = M; g.N = N; g.K = K;
+  g.A = A.p; g.lda = A.ld; g.sA0 = A.s0; g.at = A.trans;
+  g.B = B.p; g.ldb = B.ld; g.sB1 = B.s1; g.bt = B.trans;
+  g.C = C.p; g.ldc = C.ld; g.sC0 = C.s0; g.sC1 = C.s1;
+  g.nb0 = nb0; g.nb1 = nb1;
+  g.kp = kp;
+  // about four workgroups per compute unit, each reusing its A tile over
+  // `group` batches of B
+  const int64_t base = (int64_t)nb0 * g.mtiles;
+  g.group = (int)std::max<int64_t>(1, std::min<int64_t>(nb1, cdiv(base * nb1, 1024)));
+  const dim3 grid((unsigned)base, (unsigned)cdiv(nb1, g.group));
+  const size_t lds = (size_t)(g.mt + np) * kp * es;
+#define CTM_SB(T, KS_, NT_) small_batch_kernel<T, KS_, NT_><<<grid, 256, lds, s>>>(g)
+  // (ks, nt) is exactly one of the instances below
+  if (e == DType::BF16) {
+    if (nt == 1) CTM_SB(bf16, 2, 1);
+    else CTM_SB(bf16, 2, 4);
+  } else if (e == DType::F32) {
+    if (ks == 1) CTM_SB(float, 1, 1);
+    else if (ks == 4) CTM_SB(float, 4, 1);
+    else if (ks == 9) CTM_SB(float, 9, 3);
+    else CTM_SB(float, 16, 4);
+  } else {
+    if (ks == 1) CTM_SB(double, 1, 1);
+    else if (ks == 4) CTM_SB(double, 4, 1);
+    else if (ks == 9) CTM_SB(double, 9, 3);
+    else CTM_SB(double, 16, 4);
+  }
+#undef CTM_SB
+  CTM_LAUNCHED();
+  return true;
+}
+
+}  // namespace
+
 constexpr int MAX_SPLIT = 16;
 
 size_t gemm_scratch_bytes(DType e, int M, int N) {
@@ -424,6 +626,9 @@ void gemm(hipStream_t s, DType e, int M, int N, int K, const Operand& A, const O
           const Output& C, int nb0, int nb1, double alpha, double beta, const Scratch& ws,
           int ksplit, double* sumsq, const KernelEvents* ev) {
   if (M <= 0 || N <= 0 || nb0 <= 0 || nb1 <= 0) return;
+  if (ksplit == 0 && sumsq == nullptr && ev == nullptr &&
+      small_batch(s, e, M, N, K, A, B, C, nb0, nb1, alpha, beta))
+    return;
   const int cfg = pick_cfg(M, N);
   const int BM = CFGS[cfg].BM, BN = CFGS[cfg].BN;
   const int BK = 128 / (int)dtype_size(e);

@@ -119,6 +119,38 @@ def test_gemm_two_level_batch(prec):
     assert err.max() < max(TOL[prec], TOL_OUT[prec]), err.max()
 
 
+@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("nb0,nb1,M,N,K,ta,tb", [(5, 7, 144, 36, 36, True, False),
+                                                  (3, 4, 256, 64, 64, True, False),
+                                                  (4, 3, 100, 20, 50, False, True),
+                                                  (2, 5, 17, 64, 3, False, False),
+                                                  (3, 2, 40, 9, 64, True, True)])
+def test_gemm_small_batches(prec, nb0, nb1, M, N, K, ta, tb):
+    """Batched products with K, N <= 64 and A shared across the second batch
+    index (the pair contractions of the enlarged corner), several row tiles
+    of A, both operand layouts; C[b0][b1] lives in a padded row layout."""
+    r = _rng(nb0 * 1009 + nb1 * 101 + M + N + K + prec + 2 * ta + tb)
+    A = r.standard_normal((nb0,) + ((K, M) if ta else (M, K)))
+    B = r.standard_normal((nb1,) + ((N, K) if tb else (K, N)))
+    ldc = N + 3
+    Ad = torch.tensor(A, device=DEV).to(TDT[prec])
+    Bd = torch.tensor(B, device=DEV).to(TDT[prec])
+    Cd = torch.full((nb0, nb1, M, ldc), 7.0, device=DEV, dtype=TDT[prec])
+    ctm.gemm(Ad, Bd, Cd, M, N, K, lda=M if ta else K, ldb=K if tb else N, ldc=ldc, transA=ta,
+             transB=tb, prec=prec, batch=(nb0, nb1), sA=(K * M, 0), sB=(0, K * N),
+             sC=(nb1 * M * ldc, M * ldc))
+    torch.cuda.synchronize()
+    Ah, Bh = _stored(A, prec), _stored(B, prec)
+    opA = np.swapaxes(Ah, 1, 2) if ta else Ah
+    opB = np.swapaxes(Bh, 1, 2) if tb else Bh
+    ref = np.einsum("amk,bkn->abmn", opA, opB)
+    scale = np.einsum("amk,bkn->abmn", np.abs(opA), np.abs(opB)) + 1e-300
+    out = Cd.double().cpu().numpy()
+    err = (np.abs(out[..., :N] - ref) / scale).max()
+    assert err < max(TOL[prec], TOL_OUT[prec]), err
+    assert np.all(out[..., N:] == 7.0)  # padding columns untouched
+
+
 QR_SHAPES = [(16, 16), (40, 16), (200, 37), (1024, 64), (1600, 100), (5184, 144), (144, 144),
              (513, 33), (1025, 64), (9000, 100), (16384, 256), (30000, 40), (7, 1)]
 
