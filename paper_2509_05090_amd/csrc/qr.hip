@@ -35,13 +35,16 @@ constexpr int QW = QT / 64;
 
 typedef double d4v __attribute__((ext_vector_type(4)));
 
+constexpr int QTR_MAX = 64;  // most register rows per lane group
+
 template <int NBT>
-struct QrShared {
-  double red[2][QW][NBT];   // per-wavefront partial sums per window position
-  double piv[2][NBT];       // pivot row
+struct __attribute__((aligned(16))) QrShared {
+  alignas(16) double xs[QW][4][QTR_MAX];  // per wavefront and row group: the pivot column
+  double red[2][QW][NBT];     // per-wavefront partial dots (by column parity)
+  double piv[2][NBT];         // pivot row (by column parity)
+  double R[NBT][NBT + 1];     // rows of R as they are finished
+  double G[NBT][NBT + 1];     // Gram matrix of the reflectors (strictly upper part)
   double tau[NBT];
-  double G[NBT][NBT + 1];   // Gram matrix of the reflectors
-  double Gp[QW][NBT][NBT + 1];
   int last;
 };
 
@@ -55,127 +58,124 @@ __device__ __forceinline__ double mk64(unsigned lo, unsigned hi) {
   return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
-// Exchange across the two halves of the wavefront (lanes l and l^32) or of
-// each 32-lane half (l and l^16): with x the value of the lower index half
-// and y that of the upper, the permlane swaps leave in every lane its own
-// kept value plus its partner's copy of it, so the sum is the pair sum of
-// the half the lane keeps (lower half if the lane's bit is 0).
-__device__ __forceinline__ double pair_sum32(double x, double y) {
-  const auto l = __builtin_amdgcn_permlane32_swap(lo32(x), lo32(y), false, false);
-  const auto h = __builtin_amdgcn_permlane32_swap(hi32(x), hi32(y), false, false);
+// Sum of v over lanes l and l^32 (permlane32 swap), resp. l and l^16
+// (permlane16 swap), in every lane.
+__device__ __forceinline__ double sum_x32(double v) {
+  const auto l = __builtin_amdgcn_permlane32_swap(lo32(v), lo32(v), false, false);
+  const auto h = __builtin_amdgcn_permlane32_swap(hi32(v), hi32(v), false, false);
   return mk64(l[0], h[0]) + mk64(l[1], h[1]);
 }
-__device__ __forceinline__ double pair_sum16(double x, double y) {
-  const auto l = __builtin_amdgcn_permlane16_swap(lo32(x), lo32(y), false, false);
-  const auto h = __builtin_amdgcn_permlane16_swap(hi32(x), hi32(y), false, false);
+__device__ __forceinline__ double sum_x16(double v) {
+  const auto l = __builtin_amdgcn_permlane16_swap(lo32(v), lo32(v), false, false);
+  const auto h = __builtin_amdgcn_permlane16_swap(hi32(v), hi32(v), false, false);
   return mk64(l[0], h[0]) + mk64(l[1], h[1]);
 }
 
-// Value of the partner lane within a row of 16 lanes through DPP: row_ror:8
-// (partner l^8), row_half_mirror (partner 7-l within 8: differs in bit 2),
-// quad_perm [2,3,0,1] (l^2) and [1,0,3,2] (l^1).
-template <int CTRL>
-__device__ __forceinline__ double dpp64(double v) {
-  const int l = __builtin_amdgcn_update_dpp(0, (int)lo32(v), CTRL, 0xF, 0xF, false);
-  const int h = __builtin_amdgcn_update_dpp(0, (int)hi32(v), CTRL, 0xF, 0xF, false);
-  return mk64((unsigned)l, (unsigned)h);
-}
-
-// Value of lane k (uniform) of v, in every lane.
-__device__ __forceinline__ double bcast64(double v, int k) {
-  return mk64((unsigned)__builtin_amdgcn_readlane((int)lo32(v), k),
-              (unsigned)__builtin_amdgcn_readlane((int)hi32(v), k));
-}
-
-template <int N, int CTRL>
-__device__ __forceinline__ void rs_halve(const double (&in)[2 * N], double (&out)[N], bool up) {
-#pragma unroll
-  for (int j = 0; j < N; ++j) {
-    const double keep = up ? in[j + N] : in[j], send = up ? in[j] : in[j + N];
-    out[j] = keep + dpp64<CTRL>(send);
-  }
-}
-
-// Reduce-scatter of NBT per-lane values f[0..NBT) over the wavefront.  On
-// return every lane holds the wavefront sum of index rs_index<NBT>(lane).
+// Register layout of a row block of at most 16 TR rows held by the 256
+// threads: lane l = 16 g + i of wavefront v holds, in a[t][h], row
+// 4 (TR v + t) + g (t < TR) of column i + 16 h (h < NBT / 16).  A column is
+// then spread over the 4 row groups g (and the 4 wavefronts), a row over the
+// 16 lanes i of a row group.  Rows 0 .. NBT-1 (the diagonal block) are in
+// wavefront 0, registers t < NBT / 4.
 template <int NBT>
-__device__ __forceinline__ int rs_index(int lane) {
-  if constexpr (NBT == 32)
-    return ((lane >> 5) & 1) * 16 + ((lane >> 4) & 1) * 8 + ((lane >> 3) & 1) * 4 +
-           ((lane >> 2) & 1) * 2 + ((lane >> 1) & 1);
-  else
-    return ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 + ((lane >> 3) & 1) * 2 +
-           ((lane >> 2) & 1);
-}
-// Lanes holding a distinct index (the others hold copies).
-template <int NBT>
-__device__ __forceinline__ bool rs_writer(int lane) {
-  return NBT == 32 ? (lane & 1) == 0 : (lane & 3) == 0;
-}
+constexpr int slots_of() { return NBT / 16; }
 
-// Column at window position P (absolute column c) of the local Householder
-// QR; rows t = tid + r * QT held in a[r][*].
-template <int NBT, int RPT, int P>
-__device__ __forceinline__ void qr_column(double (&a)[RPT][NBT], int c, QrShared<NBT>& sh,
-                                          int tid) {
-  const int lane = tid & 63, wid = tid >> 6;
-  const int buf = c & 1;
-  double x[RPT];
+// Householder step for column k (slot H = k / 16) of the row block.
+//   - lanes holding column k publish it below the diagonal (x, zero at and
+//     above row k) through wavefront-private LDS; every lane reads the
+//     values of its own row group;
+//   - partial dots x . a_c over the lane's rows, summed over the 4 row groups
+//     of the wavefront (permlane swaps), then over the wavefronts through
+//     LDS: one barrier per column;
+//   - the reflector follows LAPACK's dlarfg (beta = -sign(x0) ||(x0, x)||,
+//     v = (1, x / (x0 - beta)), tau = (beta - x0) / beta); a column that is
+//     already zero below the diagonal gets I - 2 e e^T (tau = 2);
+//   - row k of R is final and goes to LDS; rows below are updated,
+//     a_c -= tau v (v . a_c) for the later columns c; the earlier columns and
+//     column k itself keep their values (column k keeps x, the reflector up
+//     to its scale);
+//   - v_c . v_k = scale_c w_c for the earlier columns c, where w_c = v . a_c,
+//     so the Gram matrix of the reflectors is filled in on the way.
+template <int NBT, int TR, int H>
+__device__ __forceinline__ void qr_column(double (&a)[TR][NBT / 16], double (&sc)[NBT / 16],
+                                          int k, QrShared<NBT>& sh) {
+  constexpr int SL = NBT / 16;
+  constexpr int TD = NBT / 4;  // registers holding the diagonal block (wavefront 0)
+  const int lane = threadIdx.x & 63;
+  const int v = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform
+  const int g = lane >> 4, i = lane & 15;
+  const int par = k & 1;
+  // 1. the pivot column below the diagonal, to the lanes of each row group
+  //    (only wavefront 0 holds rows at or above the pivot)
+  if (i == (k & 15)) {
+    if (v == 0) {
 #pragma unroll
-  for (int r = 0; r < RPT; ++r) x[r] = tid + r * QT > c ? a[r][P] : 0.0;
-  double hsum;
-  if constexpr (NBT == 32) {
-    double h16[16], h8[8], h4[4], h2[2], h1[1];
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      double lo = 0.0, hi = 0.0;
-#pragma unroll
-      for (int r = 0; r < RPT; ++r) {
-        if (j >= P) lo += x[r] * a[r][j];
-        hi += x[r] * a[r][j + 16];
+      for (int t = 0; t < TR; t += 2) {
+        double x0 = a[t][H], x1 = a[t + 1][H];
+        if (t < TD) {
+          if (4 * t + g <= k) x0 = 0.0;
+          if (4 * (t + 1) + g <= k) x1 = 0.0;
+        }
+        *(double2*)&sh.xs[v][g][t] = double2{x0, x1};
       }
-      h16[j] = pair_sum32(lo, hi);
+    } else {
+#pragma unroll
+      for (int t = 0; t < TR; t += 2) *(double2*)&sh.xs[v][g][t] = double2{a[t][H], a[t + 1][H]};
     }
-#pragma unroll
-    for (int j = 0; j < 8; ++j) h8[j] = pair_sum16(h16[j], h16[j + 8]);
-    rs_halve<4, 0x128>(h8, h4, lane & 8);
-    rs_halve<2, 0x141>(h4, h2, lane & 4);
-    rs_halve<1, 0x4E>(h2, h1, lane & 2);
-    hsum = h1[0] + dpp64<0xB1>(h1[0]);
-  } else {
-    double h8[8], h4[4], h2[2], h1[1];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      double lo = 0.0, hi = 0.0;
-#pragma unroll
-      for (int r = 0; r < RPT; ++r) {
-        if (j >= P) lo += x[r] * a[r][j];
-        hi += x[r] * a[r][j + 8];
-      }
-      h8[j] = pair_sum32(lo, hi);
-    }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) h4[j] = pair_sum16(h8[j], h8[j + 4]);
-    rs_halve<2, 0x128>(h4, h2, lane & 8);
-    rs_halve<1, 0x141>(h2, h1, lane & 4);
-    hsum = h1[0] + dpp64<0x4E>(h1[0]);
-    hsum = hsum + dpp64<0xB1>(hsum);
   }
-  if (rs_writer<NBT>(lane)) sh.red[buf][wid][rs_index<NBT>(lane)] = hsum;
-  const bool pivot = tid == c;
-  if (pivot) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  double x[TR];
 #pragma unroll
-    for (int q = 0; q < NBT; ++q) sh.piv[buf][q] = a[0][q];
+  for (int t = 0; t < TR; t += 2) {
+    const double2 p = *(const double2*)&sh.xs[v][g][t];
+    x[t] = p.x;
+    x[t + 1] = p.y;
+  }
+  // 2. partial dots with the lane's columns, summed over the wavefront
+  double d[SL];
+#pragma unroll
+  for (int h = 0; h < SL; ++h) {
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int t = 0; t < TR; t += 2) {
+      s0 += x[t] * a[t][h];
+      s1 += x[t + 1] * a[t + 1][h];
+    }
+    d[h] = sum_x16(sum_x32(s0 + s1));
+  }
+  if (g == 0) {
+#pragma unroll
+    for (int h = 0; h < SL; ++h) sh.red[par][v][i + 16 * h] = d[h];
+  }
+  // the pivot row (row k: wavefront 0, row group k & 3, register k >> 2)
+  if (v == 0 && g == (k & 3)) {
+    const int tk = k >> 2;
+#pragma unroll
+    for (int h = 0; h < SL; ++h) {
+      double pv = a[0][h];
+#pragma unroll
+      for (int t = 1; t < TD; ++t)
+        if (t == tk) pv = a[t][h];
+      sh.piv[par][i + 16 * h] = pv;
+    }
   }
   __syncthreads();
-  // Every wavefront forms the full sums itself: lane k < NBT holds the sum and
-  // the pivot row value of window position k; the rest is read by broadcast.
-  const int kl = lane & (NBT - 1);
-  double f = 0.0;
+  // 3. full dots of the lane's columns and the reflector
+  double f[SL], p[SL];
 #pragma unroll
-  for (int v = 0; v < QW; ++v) f += sh.red[buf][v][kl];
-  const double pk = sh.piv[buf][kl];
-  const double x0 = bcast64(pk, P), sigma = bcast64(f, P);
+  for (int h = 0; h < SL; ++h) {
+    double s = 0.0;
+#pragma unroll
+    for (int u = 0; u < QW; ++u) s += sh.red[par][u][i + 16 * h];
+    f[h] = s;
+    p[h] = sh.piv[par][i + 16 * h];
+  }
+  double sigma = 0.0;
+#pragma unroll
+  for (int u = 0; u < QW; ++u) sigma += sh.red[par][u][k];
+  const double x0 = sh.piv[par][k];
   double beta, tau, scale;
   if (sigma == 0.0) {
     tau = 2.0;
@@ -187,138 +187,114 @@ __device__ __forceinline__ void qr_column(double (&a)[RPT][NBT], int c, QrShared
     tau = (beta - x0) / beta;
     scale = 1.0 / (x0 - beta);
   }
-  if (tid == 0) sh.tau[c & (NBT - 1)] = tau;
-  const double wlane = pk + scale * f;  // v^T a_k for k = lane
-  // reflector entries of this thread's rows: x scale below the pivot, 1 on
-  // it, 0 above
-  double tv[RPT], v[RPT];
+  if (i == (k & 15)) sc[H] = scale;
+  double wv[SL], uv[SL];
 #pragma unroll
-  for (int r = 0; r < RPT; ++r) {
-    v[r] = x[r] * scale;
-    if (r == 0 && pivot) v[r] = 1.0;
-    tv[r] = tau * v[r];
+  for (int h = 0; h < SL; ++h) {
+    wv[h] = p[h] + scale * f[h];  // v . a_c
+    uv[h] = (i + 16 * h > k) ? tau * scale * wv[h] : 0.0;
   }
-  // later columns: a_k -= tau v (v^T a_k)
+  if (v == 0 && g == 0) {
 #pragma unroll
-  for (int k = P + 1; k < NBT; ++k) {
-    const double wk = bcast64(wlane, k);
-#pragma unroll
-    for (int r = 0; r < RPT; ++r) a[r][k] -= tv[r] * wk;
+    for (int h = 0; h < SL; ++h) {
+      const int c = i + 16 * h;
+      sh.R[k][c] = c > k ? p[h] - tau * wv[h] : (c == k ? beta : 0.0);
+      if (c < k) sh.G[c][k] = sc[h] * wv[h];
+    }
+    if (i == 0) sh.tau[k] = tau;
   }
-  // column c: the reflector below the pivot, beta on it
+  // 4. rows below the pivot (x is zero at and above it)
 #pragma unroll
-  for (int r = 0; r < RPT; ++r)
-    if (tid + r * QT > c) a[r][P] = v[r];
-  if (pivot) a[0][P] = beta;
+  for (int t = 0; t < TR; ++t)
+#pragma unroll
+    for (int h = 0; h < SL; ++h) a[t][h] -= x[t] * uv[h];
 }
 
-// Local Householder QR of m rows x w columns held in registers.  Writes the
-// reflectors to Y (m x w, unit diagonal, zeros above; leading dimension
-// ldy), R to Rd (w x w upper triangle, zeros below; leading dimension ldr)
-// and the compact WY factor to Tout (NBT x NBT, zero outside w x w).
-template <int NBT, int RPT>
-__device__ __forceinline__ void local_qr(double (&a)[RPT][NBT], int m, int w, QrShared<NBT>& sh,
-                                         int tid, double* __restrict__ Y, int64_t ldy,
+// Householder QR of a block of m rows x w columns held in registers (layout
+// above).  Writes the reflectors to Y (m x w, unit diagonal, zeros above;
+// leading dimension ldy), R to Rd (w x w upper triangle, zeros below;
+// leading dimension ldr) and the compact WY factor to Tout (NBT x NBT, zero
+// outside w x w): T^{-1} = diag(1/tau) + strictly-upper(Y^T Y) (Joffrain,
+// Low, Quintana-Orti, van de Geijn, Van Zee, ACM TOMS 32 (2006)).
+template <int NBT, int TR>
+__device__ __forceinline__ void local_qr(double (&a)[TR][NBT / 16], int m, int w,
+                                         QrShared<NBT>& sh, double* __restrict__ Y, int64_t ldy,
                                          double* __restrict__ Rd, int64_t ldr,
                                          double* __restrict__ Tout) {
+  constexpr int SL = NBT / 16;
+  const int tid = threadIdx.x, lane = tid & 63, v = tid >> 6;
+  const int g = lane >> 4, i = lane & 15;
+  double sc[SL];
+#pragma unroll
+  for (int h = 0; h < SL; ++h) sc[h] = 0.0;
+  // G is written only for column pairs inside w; the rest must read as zero
+  for (int idx = tid; idx < NBT * (NBT + 1); idx += QT) (&sh.G[0][0])[idx] = 0.0;
+  __syncthreads();
 #pragma unroll 1
-  for (int c0 = 0; c0 < w; c0 += 4) {
-    qr_column<NBT, RPT, 0>(a, c0, sh, tid);
-    if (c0 + 1 < w) qr_column<NBT, RPT, 1>(a, c0 + 1, sh, tid);
-    if (c0 + 2 < w) qr_column<NBT, RPT, 2>(a, c0 + 2, sh, tid);
-    if (c0 + 3 < w) qr_column<NBT, RPT, 3>(a, c0 + 3, sh, tid);
-    // write out the four finished columns, then shift the window
+  for (int k = 0; k < min(w, 16); ++k) qr_column<NBT, TR, 0>(a, sc, k, sh);
+  if constexpr (SL == 2) {
+#pragma unroll 1
+    for (int k = 16; k < w; ++k) qr_column<NBT, TR, 1>(a, sc, k, sh);
+  }
+  // reflectors: Y[r][c] = scale_c x_c[r] below the diagonal, 1 on it
 #pragma unroll
-    for (int r = 0; r < RPT; ++r) {
-      const int t = tid + r * QT;
+  for (int t = 0; t < TR; ++t) {
+    const int r = 4 * (TR * v + t) + g;
 #pragma unroll
-      for (int p = 0; p < 4; ++p) {
-        const int c = c0 + p;
-        if (c < w && t < m) {
-          Y[(int64_t)t * ldy + c] = t > c ? a[r][p] : (t == c ? 1.0 : 0.0);
-          if (t < w) Rd[(int64_t)t * ldr + c] = t <= c ? a[r][p] : 0.0;
-        }
-      }
-#pragma unroll
-      for (int q = 0; q + 4 < NBT; ++q) a[r][q] = a[r][q + 4];
-#pragma unroll
-      for (int q = NBT - 4; q < NBT; ++q) a[r][q] = 0.0;
+    for (int h = 0; h < SL; ++h) {
+      const int c = i + 16 * h;
+      if (r < m && c < w) Y[(int64_t)r * ldy + c] = r > c ? sc[h] * a[t][h] : (r == c ? 1.0 : 0.0);
     }
   }
-  __syncthreads();  // Y written by this workgroup is read back below
-  // Gram matrix G = Y^T Y on the matrix cores: 16x16 tiles (ti, tj), ti <= tj;
-  // wavefront wid takes the 4-row steps k0 = 4 (wid + QW s).
-  const int lane = tid & 63, wid = tid >> 6, i16 = lane & 15, grp = lane >> 4;
-  constexpr int NT = NBT / 16;
-  d4v acc[NT][NT];
-#pragma unroll
-  for (int i = 0; i < NT; ++i)
-#pragma unroll
-    for (int j = 0; j < NT; ++j) acc[i][j] = d4v{0.0, 0.0, 0.0, 0.0};
-  // The loads of a batch of steps are all issued before its products (Y was
-  // just written, so each load is a full trip to the L2).
-  constexpr int KB = 8;
-  for (int kb = 4 * wid; kb < m; kb += 4 * QW * KB) {
-    double y[KB][NT];
-#pragma unroll
-    for (int s = 0; s < KB; ++s) {
-      const int t = kb + 4 * QW * s + grp;
-#pragma unroll
-      for (int i = 0; i < NT; ++i) {
-        const int q = 16 * i + i16;
-        y[s][i] = (t < m && q < w) ? Y[(int64_t)t * ldy + q] : 0.0;
-      }
-    }
-#pragma unroll
-    for (int s = 0; s < KB; ++s) {
-      if (kb + 4 * QW * s < m) {
-#pragma unroll
-        for (int i = 0; i < NT; ++i)
-#pragma unroll
-          for (int j = i; j < NT; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(y[s][i], y[s][j], acc[i][j], 0, 0, 0);
-      }
-    }
+  __syncthreads();  // R, G and tau complete
+  for (int idx = tid; idx < w * w; idx += QT) {
+    const int r = idx / w, c = idx % w;
+    Rd[(int64_t)r * ldr + c] = sh.R[r][c];
   }
-  // result layout: register e of lane (grp, i16) holds row 4 e + grp, column i16
-#pragma unroll
-  for (int i = 0; i < NT; ++i)
-#pragma unroll
-    for (int j = i; j < NT; ++j)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) sh.Gp[wid][16 * i + 4 * e + grp][16 * j + i16] = acc[i][j][e];
-  __syncthreads();
-  for (int idx = tid; idx < NBT * NBT; idx += QT) {
-    const int i = idx / NBT, j = idx % NBT;
-    double g = 0.0;
-#pragma unroll
-    for (int v = 0; v < QW; ++v) g += sh.Gp[v][i][j];
-    sh.G[i][j] = g;  // valid for i, j in the computed (upper) tiles
-  }
-  __syncthreads();
   // T = (diag(1/tau) + strictly-upper(G))^{-1}, by back substitution with
   // one column of T per lane of wavefront 0.
   if (tid < 64) {
     const int j = tid;
     double tc[NBT];
 #pragma unroll
-    for (int i = NBT - 1; i >= 0; --i) {
-      double s0 = i == j ? 1.0 : 0.0, s1 = 0.0;
+    for (int ii = NBT - 1; ii >= 0; --ii) {
+      double s0 = ii == j ? 1.0 : 0.0, s1 = 0.0;
 #pragma unroll
-      for (int k = i + 1; k < NBT; ++k) {
-        if ((k - i) & 1) s0 -= sh.G[i][k] * tc[k];
-        else s1 -= sh.G[i][k] * tc[k];
+      for (int kk = ii + 1; kk < NBT; ++kk) {
+        if ((kk - ii) & 1) s0 -= sh.G[ii][kk] * tc[kk];
+        else s1 -= sh.G[ii][kk] * tc[kk];
       }
-      tc[i] = (i < w && j < w && i <= j) ? sh.tau[i] * (s0 + s1) : 0.0;
+      tc[ii] = (ii < w && j < w && ii <= j) ? sh.tau[ii] * (s0 + s1) : 0.0;
     }
     if (j < NBT) {
 #pragma unroll
-      for (int i = 0; i < NBT; ++i) Tout[i * NBT + j] = tc[i];
+      for (int ii = 0; ii < NBT; ++ii) Tout[ii * NBT + j] = tc[ii];
+    }
+  }
+  __syncthreads();  // LDS reused by the next block
+}
+
+template <int NBT, int TR>
+__device__ __forceinline__ void load_block(double (&a)[TR][NBT / 16], const double* __restrict__ src,
+                                           int64_t ld, int m, int w) {
+  constexpr int SL = NBT / 16;
+  const int lane = threadIdx.x & 63, v = threadIdx.x >> 6;
+  const int g = lane >> 4, i = lane & 15;
+#pragma unroll
+  for (int t = 0; t < TR; ++t) {
+    const int r = 4 * (TR * v + t) + g;
+#pragma unroll
+    for (int h = 0; h < SL; ++h) {
+      const int c = i + 16 * h;
+      a[t][h] = (r < m && c < w) ? src[(int64_t)r * ld + c] : 0.0;
     }
   }
 }
 
-template <int NBT, int RL, int RT>
+// Panel factorization: workgroup `leaf` factors rows [j0 + leaf rpl, ...) of
+// columns [j0, j0 + w) (TRL register rows per lane group); the last leaf to
+// finish factors the L stacked w x w triangles (TRT register rows).
+template <int NBT, int TRL, int TRT>
 __global__ __launch_bounds__(QT) void qr_panel_kernel(double* __restrict__ A, int ld, int n, int j0,
                                                       int w, int rpl, int L, double* __restrict__ Y,
                                                       int ldy, double* __restrict__ Tl,
@@ -330,18 +306,12 @@ __global__ __launch_bounds__(QT) void qr_panel_kernel(double* __restrict__ A, in
   const int r0 = j0 + leaf * rpl;
   const int m = min(rpl, n - r0);
   {
-    double a[RL][NBT];
-#pragma unroll
-    for (int r = 0; r < RL; ++r) {
-      const int t = tid + r * QT;
-      const double* row = A + (int64_t)(r0 + t) * ld + j0;
-#pragma unroll
-      for (int q = 0; q < NBT; ++q) a[r][q] = (t < m && q < w) ? row[q] : 0.0;
-    }
+    double a[TRL][NBT / 16];
+    load_block<NBT, TRL>(a, A + (int64_t)r0 * ld + j0, ld, m, w);
     double* Rd = L == 1 ? A + (int64_t)r0 * ld + j0 : S + (int64_t)leaf * w * NBT;
     const int64_t ldr = L == 1 ? ld : NBT;
-    local_qr<NBT, RL>(a, m, w, sh, tid, Y + (int64_t)r0 * ldy + j0, ldy, Rd, ldr,
-                      Tl + (int64_t)leaf * NBT * NBT);
+    local_qr<NBT, TRL>(a, m, w, sh, Y + (int64_t)r0 * ldy + j0, ldy, Rd, ldr,
+                       Tl + (int64_t)leaf * NBT * NBT);
   }
   if (L == 1) return;
   // Publish the stacked factor; the last leaf to arrive factors the stack.
@@ -352,14 +322,9 @@ __global__ __launch_bounds__(QT) void qr_panel_kernel(double* __restrict__ A, in
   if (!sh.last) return;
   __threadfence();
   const int Sm = L * w;
-  double b[RT][NBT];
-#pragma unroll
-  for (int r = 0; r < RT; ++r) {
-    const int t = tid + r * QT;
-#pragma unroll
-    for (int q = 0; q < NBT; ++q) b[r][q] = (t < Sm && q < w) ? S[(int64_t)t * NBT + q] : 0.0;
-  }
-  local_qr<NBT, RT>(b, Sm, w, sh, tid, Yt, NBT, A + (int64_t)j0 * ld + j0, ld, Tt);
+  double b[TRT][NBT / 16];
+  load_block<NBT, TRT>(b, S, NBT, Sm, w);
+  local_qr<NBT, TRT>(b, Sm, w, sh, Yt, NBT, A + (int64_t)j0 * ld + j0, ld, Tt);
   if (tid == 0) atomicExch(counter, 0u);
 }
 
@@ -516,16 +481,22 @@ void launch_panel(hipStream_t s, const QrPanel& p, double* A, int ld, int n, QrW
   double* Tt = tt_of(w, p.nb, panel);
   unsigned* cnt = w.counter + panel;
   const dim3 grid(p.L);
-#define CTM_QR_PANEL(NBT, RL, RT)                                                            \
-  qr_panel_kernel<NBT, RL, RT><<<grid, QT, 0, s>>>(A, ld, n, p.j0, p.w, p.rpl, p.L, w.Y, w.k, \
-                                                    Tl, w.S, Yt, Tt, cnt)
+#define CTM_QR_PANEL(NBT, TRL, TRT)                                                             \
+  qr_panel_kernel<NBT, TRL, TRT><<<grid, QT, 0, s>>>(A, ld, n, p.j0, p.w, p.rpl, p.L, w.Y, w.k, \
+                                                      Tl, w.S, Yt, Tt, cnt)
   if (p.nb == 32) {
-    if (p.rpt_leaf == 1) CTM_QR_PANEL(32, 1, 1);
-    else if (p.rpt_tree == 1) CTM_QR_PANEL(32, 2, 1);
-    else CTM_QR_PANEL(32, 2, 2);
+    if (p.tr_leaf == 8) CTM_QR_PANEL(32, 8, 8);
+    else if (p.tr_leaf == 16) CTM_QR_PANEL(32, 16, 8);
+    else if (p.tr_leaf == 24) CTM_QR_PANEL(32, 24, 8);
+    else if (p.tr_tree == 8) CTM_QR_PANEL(32, 32, 8);
+    else if (p.tr_tree == 16) CTM_QR_PANEL(32, 32, 16);
+    else if (p.tr_tree == 24) CTM_QR_PANEL(32, 32, 24);
+    else CTM_QR_PANEL(32, 32, 32);
   } else {
-    if (p.rpt_tree == 1) CTM_QR_PANEL(16, 4, 1);
-    else CTM_QR_PANEL(16, 4, 2);
+    if (p.tr_leaf == 16) CTM_QR_PANEL(16, 16, 16);
+    else if (p.tr_leaf == 32) CTM_QR_PANEL(16, 32, 16);
+    else if (p.tr_tree == 16) CTM_QR_PANEL(16, 64, 16);
+    else CTM_QR_PANEL(16, 64, 32);
   }
 #undef CTM_QR_PANEL
   CTM_LAUNCHED();
@@ -596,11 +567,19 @@ QrPanel qr_panel_plan(int n, int k, int j0) {
   p.j0 = j0;
   p.w = std::min(p.nb, k - j0);
   const int m = n - j0;
-  p.rpt_leaf = p.nb == 32 ? (m <= QT ? 1 : 2) : 4;
-  const int b = QT * p.rpt_leaf;
-  p.L = (int)cdiv(m, b);
+  // register rows per lane group (a workgroup holds 16 tr rows): the
+  // smallest instance that holds the rows
+  auto fit = [&](int rows) {
+    if (p.nb == 32) return rows <= 128 ? 8 : rows <= 256 ? 16 : rows <= 384 ? 24 : 32;
+    return rows <= 256 ? 16 : rows <= 512 ? 32 : 64;
+  };
+  const int big = p.nb == 32 ? 32 : 64;
+  p.tr_leaf = fit(m);
+  p.L = p.tr_leaf < big ? 1 : (int)cdiv(m, 16 * big);
   p.rpl = (int)cdiv(m, p.L);
-  p.rpt_tree = p.L * p.w > QT ? 2 : 1;
+  p.tr_leaf = fit(p.rpl);
+  if (p.L > 1 && p.tr_leaf != big) p.tr_leaf = big;  // leaf instances exist for big only
+  p.tr_tree = p.L == 1 ? (p.nb == 32 ? 8 : 16) : fit(p.L * p.w);
   return p;
 }
 
@@ -611,7 +590,8 @@ void householder_qr(hipStream_t s, double* M, int ld, int n, int k, QrWork& w) {
   const int nb = nb_of(n);
   for (int panel = 0, j0 = 0; j0 < k; ++panel, j0 += nb) {
     const QrPanel p = qr_panel_plan(n, k, j0);
-    if (p.L > QR_MAX_LEAVES || p.L * p.w > QT * 2 || p.rpl < p.w)
+    if (p.L > QR_MAX_LEAVES || p.L * p.w > 16 * p.tr_tree || p.rpl > 16 * p.tr_leaf ||
+        p.rpl < p.w || (p.nb == 32 && p.tr_tree > 32))
       throw std::logic_error("householder_qr: bad panel plan");
     launch_panel(s, p, M, ld, n, w, panel);
     const int c0 = j0 + p.w;

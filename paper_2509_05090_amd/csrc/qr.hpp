@@ -26,8 +26,8 @@ struct QrPanel {
   int nb;          // panel width of this factorization (32 or 16)
   int j0, w;       // first column, width (w <= nb)
   int L, rpl;      // leaves, rows per leaf (the last one may have fewer)
-  int rpt_leaf;    // rows per thread in the leaf workgroups
-  int rpt_tree;    // rows per thread in the stacked factorization
+  int tr_leaf;     // register rows per lane group in the leaf workgroups (16 tr rows each)
+  int tr_tree;     // register rows per lane group in the stacked factorization
 };
 
 // Device workspace of one factorization.  Carved from one allocation of
