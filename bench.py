@@ -85,9 +85,11 @@ def gpu_converged(ctm, torch, A, G, chi, prec, tol, max_steps, h):
     return e, s, steps, delta, ok, dt
 
 
-def gradient_leg(ctm, torch, ci):
-    """Fixed-point gradient on the D=4, chi=100 KH workload: converge, then
-    time ctm_grad."""
+def gradient_leg(ctm, torch, ci, np, n_dirs):
+    """Fixed-point gradient on the D=4, chi=100 KH workload: converge, time
+    ctm_grad, and compare <g, v> with central differences (h = 1e-6) of
+    converged energies along the first n_dirs seeded symmetric directions
+    (each perturbed run starts from the converged environment)."""
     w = ci.WORKLOADS["c4"]
     h = ci.site_energy_operator(w)
     dev = torch.device("cuda:0")
@@ -104,10 +106,28 @@ def gradient_leg(ctm, torch, ci):
         g, e, iters, gok = c.grad(h, mode=0, tol=1e-12)
         torch.cuda.synchronize()
         t_grad = time.perf_counter() - t1
-    return {"workload": "d=2 D=4 chi=100 Kitaev-Heisenberg phi=0.3pi, FP64",
-            "converge_steps": steps, "converge_s": t_conv, "adjoint_steps": iters,
-            "grad_ms": 1e3 * t_grad, "grad_converged": gok, "e_site": e,
-            "grad_norm": float(torch.linalg.norm(g).item())}
+        env = c.get_env()
+    out = {"workload": "d=2 D=4 chi=100 Kitaev-Heisenberg phi=0.3pi, FP64",
+           "converge_steps": steps, "converge_s": t_conv, "adjoint_steps": iters,
+           "grad_ms": 1e3 * t_grad, "grad_converged": gok, "e_site": e,
+           "grad_norm": float(torch.linalg.norm(g).item())}
+    if n_dirs > 0:
+        def energy_at(At):
+            with ctm.Context(At, G, w.chi) as cc:
+                cc.set_env(*env)
+                cc.converge(1e-14, 6000, n_check=20)
+                return cc.energy(h)[0]
+
+        gn = g.cpu().numpy()
+        errs = []
+        for seed in ci.DIRECTION_SEEDS[:n_dirs]:
+            vt = ctm.symmetrize(torch.tensor(ci.direction(w, seed), device=dev))
+            vt = vt / torch.linalg.norm(vt)
+            fd = (energy_at(A + 1e-6 * vt) - energy_at(A - 1e-6 * vt)) / 2e-6
+            errs.append(abs(float(np.sum(gn * vt.cpu().numpy())) - fd))
+        out.update({"fd_directions": n_dirs, "fd_step": 1e-6, "fd_max_abs_err": max(errs),
+                    "fd_median_abs_err": float(np.median(errs))})
+    return out
 
 
 def cpu_baseline(w, sample_steps):
@@ -204,6 +224,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--modes", default="fp32,fp64,bf16")
     ap.add_argument("--no-large", action="store_true", help="skip the D=8, chi=256 leg")
+    ap.add_argument("--fd-dirs", type=int, default=20,
+                    help="finite-difference directions of the gradient leg")
     ap.add_argument("--large-steps", type=int, default=10)
     ap.add_argument("--large-grad-k", type=int, default=2)
     args = ap.parse_args()
@@ -260,7 +282,7 @@ def main():
     grad = None
     if not args.no_grad:
         log("[bench] gradient leg (D=4, chi=100)")
-        grad = gradient_leg(ctm, torch, ci)
+        grad = gradient_leg(ctm, torch, ci, np, args.fd_dirs)
         log(f"[bench] gradient: {json.dumps(grad)}")
 
     large = None

@@ -67,39 +67,72 @@ def test_fixed_point_gradient_matches_long_unrolled_limit():
     assert err < 1e-8
 
 
+def _c4_converged():
+    """D=4, chi=100 Kitaev-Heisenberg workload converged on the GPU (FP64)."""
+    w = ci.WORKLOADS["c4"]
+    A = ctm.symmetrize(torch.tensor(ci.raw_site_tensor(w), device=DEV))
+    G = torch.tensor(ci.start_matrix(w), device=DEV)
+    c = ctm.Context(A, G, w.chi)
+    c.converge(1e-14, 6000, n_check=20)
+    return w, A, G, c
+
+
+def test_c4_unrolled_gradient_matches_oracle():
+    """Full-size (D=4, chi=100, n = 1600) gradient through three tracked
+    steps from the converged GPU state, against the oracle's autograd
+    gradient from the same state: energy and symmetric gradient element by
+    element."""
+    w, A, G, c = _c4_converged()
+    h = ci.site_energy_operator(w)
+    C0, T0, P0 = c.get_env()
+    g, e, iters, ok = c.grad(h, mode=3)
+    c.close()
+    e_ref, g_ref = ograd.gradient(A.cpu().numpy(), C0.cpu().numpy(), T0.cpu().numpy(),
+                                  P0.cpu().numpy(), w.chi, 3, h)
+    err = np.abs(g.cpu().numpy() - g_ref).max() / np.abs(g_ref).max()
+    print(f"c4 k=3: |dE| {abs(e - e_ref):.2e}, grad rel err {err:.2e}")
+    assert ok and iters == 3
+    assert abs(e - e_ref) < 1e-12
+    assert err < 1e-9
+
+
 def test_gradient_properties_and_finite_differences_c4():
     """Kitaev-Heisenberg workload (D=4, chi=100): converged on the GPU,
     fixed-point gradient; <g, A> = 0 (the energy does not depend on the
     norm of A), g symmetric, and central differences (h = 1e-6) of converged
-    GPU energies along seeded symmetric directions."""
-    w = ci.WORKLOADS["c4"]
+    GPU energies along the 20 seeded symmetric directions (each perturbed
+    run starts from the converged environment of A)."""
+    w, A, G, c = _c4_converged()
     h = ci.site_energy_operator(w)
-    A = ctm.symmetrize(torch.tensor(ci.raw_site_tensor(w), device=DEV))
-    G = torch.tensor(ci.start_matrix(w), device=DEV)
-
-    def converged_energy(At):
-        with ctm.Context(At, G, w.chi) as c:
-            _, delta, ok = c.converge(1e-14, 6000, n_check=20)
-            e, _ = c.energy(h)
-        return e
-
-    with ctm.Context(A, G, w.chi) as c:
-        c.converge(1e-14, 6000, n_check=20)
-        g, e, iters, ok = c.grad(h, mode=0, tol=1e-12, max_iter=20000)
+    C0, T0, P0 = c.get_env()
+    g, e, iters, ok = c.grad(h, mode=0, tol=1e-12, max_iter=20000)
+    c.close()
     assert ok, iters
     gn = g.cpu().numpy()
     An = A.cpu().numpy()
     assert abs(np.sum(gn * An)) < 1e-10 * np.abs(gn).max()
     assert np.abs(oracle.symmetrize(gn) - gn).max() < 1e-15
+
+    def converged_energy(At):
+        with ctm.Context(At, G, w.chi) as cc:
+            cc.set_env(C0, T0, P0)
+            _, delta, okc = cc.converge(1e-14, 6000, n_check=20)
+            assert okc
+            en, _ = cc.energy(h)
+        return en
+
     hstep = 1e-6
-    for seed in ci.DIRECTION_SEEDS[:3]:
+    worst = 0.0
+    for seed in ci.DIRECTION_SEEDS:
         v = oracle.symmetrize(ci.direction(w, seed))
         v /= np.linalg.norm(v)
         vt = torch.tensor(v, device=DEV)
         fd = (converged_energy(A + hstep * vt) - converged_energy(A - hstep * vt)) / (2 * hstep)
         dot = float(np.sum(gn * v))
+        worst = max(worst, abs(dot - fd))
         print(f"direction {seed}: <g,v> = {dot:.10f}, FD = {fd:.10f}")
         assert abs(dot - fd) <= 1e-6 * max(1.0, abs(fd))
+    print(f"20 directions: max |<g,v> - FD| = {worst:.2e}")
 
 
 def test_grad_needs_truncated_environment():
