@@ -12,7 +12,9 @@ The headline `value` is the mixed-precision rate (FP32 matrix-core
 contractions with FP32 accumulation; QR, basis, normalization and energy in
 FP64); FP64 and BF16 rates are reported beside it.  For each mode the run is
 also converged to the workload tolerance and its energy and corner spectrum
-are compared with the CPU oracle's converged run (tests/golden/c3_qr.json).
+are compared with the CPU oracle's converged run (tests/golden/c3_qr.json);
+a ladder leg (BF16, then FP32, then FP64) reports the time to the FP64
+tolerance against plain FP64.
 Timed steps are bracketed by stream synchronization, inputs resident in
 HBM.  The roofline figure is for the (chi D^2) x chi x (chi D^2) matrix-core
 products, timed with HIP events on the library's stream; their HBM traffic
@@ -20,8 +22,10 @@ comes from the rocprofv3 counter summary in profiles/ when one was taken for
 the current kernel.  A gradient leg times the fixed-point adjoint on the
 D=4, chi=100 Kitaev-Heisenberg workload, and a large leg reports FP32 and
 FP64 rates and the checkpointed gradient time at D=8, chi=256 (enlarged
-corner 16384 x 16384).  The CPU baseline times the oracle itself on the host
-for a bounded sample of full-size steps.
+corner 16384 x 16384), and a projector leg times one iteration with the QR
+and with the eigendecomposition projector at D=5, chi=120, the shape of the
+paper's comparison of the two.  The CPU baseline times the oracle itself on
+the host for a bounded sample of full-size steps.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -212,6 +216,32 @@ def large_leg(ctm, torch, ci, steps, k_grad):
     return out
 
 
+def projector_leg(ctm, torch, ci, steps):
+    """Forward CTMRG iteration time with the QR projector and with the
+    eigendecomposition projector, FP64, at D=5, chi=120 (n = 3000): the shape
+    on which the paper compares the two (Sec. III.B, Fig. 5)."""
+    w = ci.WORKLOADS["p5"]
+    dev = torch.device("cuda:0")
+    A = ctm.symmetrize(torch.tensor(ci.raw_site_tensor(w), device=dev))
+    G = torch.tensor(ci.start_matrix(w), device=dev)
+    out = {"workload": "d=2 D=5 chi=120 (n = 3000), A seed 1007, start matrix seed 1014, FP64"}
+    for proj in ("qr", "evd"):
+        with ctm.Context(A, G, w.chi, proj=proj) as c:
+            c.step(3)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            c.step(steps)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        out[proj] = {"ms_per_iter": 1e3 * dt / steps, "steps": steps}
+    out["evd_over_qr"] = out["evd"]["ms_per_iter"] / out["qr"]["ms_per_iter"]
+    out["note"] = ("the eigendecomposition baseline is this library's unblocked Householder "
+                   "tridiagonalization (two kernels per column, HBM-bound) with a host "
+                   "tridiagonal eigensolver, not a tuned library eigensolver: the ratio is an "
+                   "upper bound of the QR projector's gain")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -224,6 +254,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--modes", default="fp32,fp64,bf16")
     ap.add_argument("--no-large", action="store_true", help="skip the D=8, chi=256 leg")
+    ap.add_argument("--no-projectors", action="store_true",
+                    help="skip the QR vs eigendecomposition leg (D=5, chi=120)")
     ap.add_argument("--fd-dirs", type=int, default=20,
                     help="finite-difference directions of the gradient leg")
     ap.add_argument("--large-steps", type=int, default=10)
@@ -279,6 +311,21 @@ def main():
         res[prec] = r
         log(f"[bench] {prec}: {json.dumps(r)}")
 
+    ladder = None
+    if not args.no_converge:
+        log("[bench] ladder: BF16 -> FP32 -> FP64, converged to the FP64 tolerance")
+        e, sl, steps, delta, ok, dt = gpu_converged(ctm, torch, A, G, w.chi, "ladder", w.tol, 6000, h)
+        ladder = {"converge_tol": w.tol, "converge_steps": steps, "converge_delta": delta,
+                  "converged": ok, "converge_s": dt, "e_site": e}
+        if gold_ok:
+            so = np.array(gold["spectrum"])
+            m = min(len(sl), len(so))
+            ladder["e_err_vs_oracle"] = abs(e - gold["e_site"])
+            ladder["spectrum_err_vs_oracle"] = float(np.abs(sl[:m] - so[:m]).max())
+        if "fp64" in res and "converge_s" in res["fp64"]:
+            ladder["time_to_solution_speedup_vs_fp64"] = res["fp64"]["converge_s"] / dt
+        log(f"[bench] ladder: {json.dumps(ladder)}")
+
     grad = None
     if not args.no_grad:
         log("[bench] gradient leg (D=4, chi=100)")
@@ -290,6 +337,12 @@ def main():
         log("[bench] large leg (D=8, chi=256)")
         large = large_leg(ctm, torch, ci, args.large_steps, args.large_grad_k)
         log(f"[bench] large: {json.dumps(large)}")
+
+    projectors = None
+    if not args.no_projectors:
+        log("[bench] projector leg: QR vs EVD at D=5, chi=120")
+        projectors = projector_leg(ctm, torch, ci, 10)
+        log(f"[bench] projectors: {json.dumps(projectors)}")
 
     head = "fp32" if "fp32" in res else modes[0]
     hr = res[head]
@@ -329,8 +382,10 @@ def main():
         "modes": res,
         "speedup_mixed_vs_fp64": (res["fp32"]["iters_per_s"] / res["fp64"]["iters_per_s"])
         if "fp32" in res and "fp64" in res else None,
+        "ladder": ladder,
         "gradient": grad,
         "large": large,
+        "projectors": projectors,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

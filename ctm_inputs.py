@@ -57,6 +57,8 @@ WORKLOADS = {
                    model="heisenberg", tol=1e-12),
     "c4": Workload("c4", 2, 4, 100, 1005, 1012, model="kh", tol=1e-12),
     "c5": Workload("c5", 2, 8, 256, 1006, 1013, model="heisenberg", tol=1e-8),
+    # the shape of the paper's timing comparison of the two projectors (Sec. III.B)
+    "p5": Workload("p5", 2, 5, 120, 1007, 1014, model="heisenberg", tol=1e-10),
 }
 
 KH_PHI = 0.3 * math.pi
