@@ -24,8 +24,10 @@ D=4, chi=100 Kitaev-Heisenberg workload, and a large leg reports FP32 and
 FP64 rates and the checkpointed gradient time at D=8, chi=256 (enlarged
 corner 16384 x 16384), and a projector leg times one iteration with the QR
 and with the eigendecomposition projector at D=5, chi=120, the shape of the
-paper's comparison of the two.  The CPU baseline times the oracle itself on
-the host for a bounded sample of full-size steps.
+paper's comparison of the two, and an optimization leg runs L-BFGS on the
+site tensor with the paper's 10 warm-up and 24 tracked steps per evaluation
+at D=5, chi=120.  The CPU baseline times the oracle itself on the host for a
+bounded sample of full-size steps.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -242,6 +244,26 @@ def projector_leg(ctm, torch, ci, steps):
     return out
 
 
+def optimization_leg(ctm, torch, ci, iters):
+    """L-BFGS on the site tensor at D=5, chi=120 with 10 warm-up and 24
+    tracked CTMRG steps per evaluation (the paper's setting, Sec. III.B,
+    Fig. 5): energies and time per evaluation."""
+    from paper_2509_05090_amd import optimize
+    w = ci.WORKLOADS["p5"]
+    a0 = ctm.symmetrize(torch.tensor(ci.raw_site_tensor(w), device="cuda")).cpu().numpy()
+    ev = optimize.Evaluator(torch.tensor(ci.start_matrix(w), device="cuda"), w.chi,
+                            ci.site_energy_operator(w), k=24, warmup=10, init_steps=40)
+    t0 = time.perf_counter()
+    _, energies = optimize.lbfgs(a0, ev, iters=iters)
+    dt = time.perf_counter() - t0
+    ev.close()
+    return {"workload": "d=2 D=5 chi=120 rotated Heisenberg, L-BFGS, 10 warm-up + 24 tracked "
+                        "steps per evaluation (FP64)",
+            "iterations": iters, "evaluations": ev.calls, "seconds": dt,
+            "ms_per_evaluation": 1e3 * ev.seconds / max(ev.calls, 1),
+            "e_site_first": energies[0], "e_site_last": energies[-1]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -256,6 +278,7 @@ def main():
     ap.add_argument("--no-large", action="store_true", help="skip the D=8, chi=256 leg")
     ap.add_argument("--no-projectors", action="store_true",
                     help="skip the QR vs eigendecomposition leg (D=5, chi=120)")
+    ap.add_argument("--no-opt", action="store_true", help="skip the L-BFGS leg (D=5, chi=120)")
     ap.add_argument("--fd-dirs", type=int, default=20,
                     help="finite-difference directions of the gradient leg")
     ap.add_argument("--large-steps", type=int, default=10)
@@ -344,6 +367,12 @@ def main():
         projectors = projector_leg(ctm, torch, ci, 10)
         log(f"[bench] projectors: {json.dumps(projectors)}")
 
+    opt = None
+    if not args.no_opt:
+        log("[bench] optimization leg: L-BFGS at D=5, chi=120")
+        opt = optimization_leg(ctm, torch, ci, 4)
+        log(f"[bench] optimization: {json.dumps(opt)}")
+
     head = "fp32" if "fp32" in res else modes[0]
     hr = res[head]
     bg = hr["big_gemm"]
@@ -386,6 +415,7 @@ def main():
         "gradient": grad,
         "large": large,
         "projectors": projectors,
+        "optimization": opt,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -179,6 +179,17 @@ int ctm_get_env(ctm_ctx *c, double *C_dev, double *T_dev, double *P_dev);
 int ctm_set_env(ctm_ctx *c, int chi_c, const double *C_dev, const double *T_dev, int p_rows,
                 const double *P_dev);
 
+/* Replace the site tensor of a context, keeping its environment (C, T,
+ * P_prev), its buffers and its step count (Sec. II.D, Sec. III.B: each
+ * energy evaluation of the variational optimization continues from the
+ * environment of the previous one).  A_dev: d*D^3 FP64 device array, same d
+ * and D as at ctm_init, C3v-symmetric (as for ctm_init).  The double layer
+ * (and the open double layers of the energy) are rebuilt; the spectrum
+ * history of ctm_step / ctm_converge restarts.  A rejected tensor leaves the
+ * context unchanged.  Errors: CTM_EINVAL, CTM_ENOTSYM, CTM_ENONFINITE,
+ * CTM_EDEVICE. */
+int ctm_update_tensor(ctm_ctx *c, const double *A_dev);
+
 /* Switch the contraction arithmetic of an existing context (for a precision
  * ladder: low precision far from convergence, FP64 near it). */
 int ctm_set_precision(ctm_ctx *c, int prec);

@@ -39,6 +39,7 @@ struct ctm_ctx {
 
   // FP64 state and inputs
   double *A = nullptr, *a = nullptr, *aO = nullptr, *aOr = nullptr, *G = nullptr;
+  double* Anext = nullptr;  // site tensor under check by ctm_update_tensor
   double *C = nullptr, *T = nullptr, *Cn = nullptr, *Tn = nullptr, *P = nullptr;
   // FP64 work
   double *M = nullptr, *Q = nullptr, *Cp = nullptr, *Tp = nullptr, *Xs = nullptr, *Xq = nullptr;

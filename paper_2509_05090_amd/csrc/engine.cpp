@@ -444,6 +444,7 @@ void allocate(ctm_ctx* c) {
   const int64_t D2 = c->D2, chi = c->chi, nmax = c->nmax;
   const int64_t dA = (int64_t)c->d * c->D * c->D * c->D;
   c->A = c->allocd(dA);
+  c->Anext = c->allocd(dA);
   c->a = c->allocd(D2 * D2 * D2);
   c->G = c->allocd(nmax * chi);
   c->C = c->allocd(chi * chi);
@@ -684,6 +685,41 @@ int ctm_set_env(ctm_ctx* c, int chi_c, const double* C_dev, const double* T_dev,
       CTM_HIP(hipMemcpyAsync(c->P, P_dev, (size_t)p_rows * c->chi * 8, hipMemcpyDeviceToDevice, s));
     c->chi_c = chi_c;
     c->p_rows = p_rows;
+    c->spec_step = -1;
+    return CTM_OK;
+  });
+}
+
+int ctm_update_tensor(ctm_ctx* c, const double* A_dev) {
+  if (!c || !A_dev) {
+    g_error = "ctm_update_tensor: null pointer";
+    return CTM_EINVAL;
+  }
+  return guarded(c, [&]() -> int {
+    hipStream_t s = c->stream;
+    const int64_t dA = (int64_t)c->d * c->D * c->D * c->D;
+    // checked in a scratch copy first, so a rejected tensor leaves the state as it was
+    double* chk = c->Anext;
+    CTM_HIP(hipMemcpyAsync(chk, A_dev, dA * sizeof(double), hipMemcpyDeviceToDevice, s));
+    launch_symmetry_defect(s, chk, c->d, c->D, c->dev_small);
+    double sd[2];
+    CTM_HIP(hipMemcpyAsync(sd, c->dev_small, sizeof(sd), hipMemcpyDeviceToHost, s));
+    CTM_HIP(hipStreamSynchronize(s));
+    if (!(sd[1] > 0.0) || !std::isfinite(sd[0]) || !std::isfinite(sd[1])) {
+      c->err = "site tensor is zero or not finite";
+      return CTM_ENONFINITE;
+    }
+    if (std::sqrt(sd[0]) > 1e-12 * std::sqrt(sd[1])) {
+      c->err = "site tensor is not C3v-symmetric: ||A - sym(A)|| / ||A|| = " +
+               std::to_string(std::sqrt(sd[0] / sd[1]));
+      return CTM_ENOTSYM;
+    }
+    CTM_HIP(hipMemcpyAsync(c->A, A_dev, dA * sizeof(double), hipMemcpyDeviceToDevice, s));
+    launch_double_layer(s, c->A, c->d, c->D, c->a);
+    if (c->aO) {
+      launch_double_layer_open(s, c->A, c->d, c->D, 0, c->aO);
+      launch_double_layer_open(s, c->A, c->d, c->D, 1, c->aOr);
+    }
     c->spec_step = -1;
     return CTM_OK;
   });

@@ -31,9 +31,9 @@ PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "ladder": 3}
 DTYPE_CODE = {"float64": 0, "float32": 1, "bfloat16": 2}
 
 EXPORTS = ("ctm_symmetrize", "ctm_init", "ctm_step", "ctm_converge", "ctm_energy",
-           "ctm_grad", "ctm_spectrum", "ctm_query", "ctm_get_env", "ctm_set_env", "ctm_set_precision",
-           "ctm_free", "ctm_last_error", "ctm_gemm", "ctm_qr", "ctm_eigh", "ctm_profile",
-           "ctm_profile_read")
+           "ctm_grad", "ctm_spectrum", "ctm_query", "ctm_get_env", "ctm_set_env",
+           "ctm_update_tensor", "ctm_set_precision", "ctm_free", "ctm_last_error", "ctm_gemm",
+           "ctm_qr", "ctm_eigh", "ctm_profile", "ctm_profile_read")
 STAGES = ("corner", "projector", "renorm_c", "renorm_t", "big_gemm")
 
 
@@ -65,6 +65,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "ctm_query": (i, [vp, pi, pi, pi]),
         "ctm_get_env": (i, [vp, vp, vp, vp]),
         "ctm_set_env": (i, [vp, i, vp, vp, i, vp]),
+        "ctm_update_tensor": (i, [vp, vp]),
         "ctm_set_precision": (i, [vp, i]),
         "ctm_free": (None, [vp]),
         "ctm_last_error": (ctypes.c_char_p, [vp]),
@@ -243,6 +244,12 @@ class Context:
         pr = 0 if P is None else P.shape[0]
         _check(_lib.ctm_set_env(self._h, x, _ptr(C.contiguous()), _ptr(T.contiguous()), pr,
                                 _ptr(None if P is None else P.contiguous())), self._h)
+
+    def update_tensor(self, A):
+        """ctm_update_tensor: a new C3v-symmetric site tensor (same d, D),
+        keeping the environment."""
+        assert tuple(A.shape) == (self.d, self.D, self.D, self.D)
+        _check(_lib.ctm_update_tensor(self._h, _ptr(A.contiguous())), self._h)
 
     def profile(self, enable: bool = True):
         _check(_lib.ctm_profile(self._h, int(enable)), self._h)

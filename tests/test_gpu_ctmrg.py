@@ -173,3 +173,33 @@ def test_precision_ladder_reaches_fp64_energy():
     print(f"ladder: {steps} steps, |dE| = {abs(e - gold['e_site']):.3e}")
     assert ok and delta < w.tol
     assert abs(e - gold["e_site"]) < 1e-10
+
+
+def test_update_tensor_continues_from_the_environment():
+    """ctm_update_tensor keeps C, T, P_prev: the continued run equals a fresh
+    context with the new tensor started from the same environment; a
+    tensor that is not C3v-symmetric is rejected and changes nothing."""
+    w = ci.Workload("u", 2, 3, 20, 301, 302)
+    c, A = gpu_context(w)
+    c.step(6)
+    C0, T0, P0 = c.get_env()
+    A2 = ctm.symmetrize(torch.tensor(ci.gaussian((2, 3, 3, 3), 303), device=DEV))
+    bad = A2.clone()
+    bad[0, 0, 1, 2] += 0.1
+    with pytest.raises(ctm.CtmError):
+        c.update_tensor(bad)
+    C1, T1, P1 = c.get_env()
+    assert torch.equal(C0, C1) and torch.equal(T0, T1) and torch.equal(P0, P1)
+    c.update_tensor(A2)
+    c.step(3)
+    e1, _ = c.energy(ci.heisenberg_rotated())
+    Cu, Tu, Pu = c.get_env()
+    c.close()
+    f = ctm.Context(A2, torch.tensor(ci.start_matrix(w), device=DEV), w.chi)
+    f.set_env(C0, T0, P0)
+    f.step(3)
+    e2, _ = f.energy(ci.heisenberg_rotated())
+    Cf, Tf, Pf = f.get_env()
+    f.close()
+    assert torch.equal(Cu, Cf) and torch.equal(Tu, Tf) and torch.equal(Pu, Pf)
+    assert e1 == e2
