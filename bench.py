@@ -78,8 +78,12 @@ def gpu_rate(ctm, torch, A, G, chi, prec, warmup, steps, n_check=10):
     return steps / dt, steps / dt_check, stages, flops
 
 
-def gpu_converged(ctm, torch, A, G, chi, prec, tol, max_steps, h):
-    """Converge (spectrum check every 10 steps); energy, spectrum, steps, time."""
+def gpu_converged(ctm, torch, A, G, chi, prec, tol, max_steps, h, residuals=None):
+    """Converge (spectrum check every 10 steps); energy, spectrum, steps, time.
+    If `residuals` is a dict it receives the isometry residual max|P^T P - I|
+    of the final projector and the fixed-point residual: the largest change
+    of C and T under one more step (the aligned basis makes the fixed point
+    stationary element by element)."""
     with ctm.Context(A, G, chi, prec=prec) as c:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -88,6 +92,14 @@ def gpu_converged(ctm, torch, A, G, chi, prec, tol, max_steps, h):
         dt = time.perf_counter() - t0
         e, _ = c.energy(h)
         s = c.spectrum()
+        if residuals is not None:
+            C0, T0, P0 = c.get_env()
+            eye = torch.eye(P0.shape[1], dtype=P0.dtype, device=P0.device)
+            residuals["isometry"] = float((P0.T @ P0 - eye).abs().max().item())
+            c.step(1)
+            C1, T1, _ = c.get_env()
+            residuals["fixed_point"] = float(max((C1 - C0).abs().max().item(),
+                                                 (T1 - T0).abs().max().item()))
     return e, s, steps, delta, ok, dt
 
 
@@ -322,9 +334,13 @@ def main():
                          "tflops": flops / (big_ms * 1e-3) / 1e12 if big_ms > 0 else None}
         if not args.no_converge:
             tol = {"fp64": w.tol, "fp32": 1e-8, "bf16": 1e-4}[prec]
-            e, s, steps, delta, ok, dt = gpu_converged(ctm, torch, A, G, w.chi, prec, tol, 4000, h)
+            resid = {}
+            e, s, steps, delta, ok, dt = gpu_converged(ctm, torch, A, G, w.chi, prec, tol, 4000, h,
+                                                       resid)
             r.update({"e_site": e, "converge_tol": tol, "converge_steps": steps,
-                      "converge_delta": delta, "converged": ok, "converge_s": dt})
+                      "converge_delta": delta, "converged": ok, "converge_s": dt,
+                      "isometry_residual": resid["isometry"],
+                      "fixed_point_residual": resid["fixed_point"]})
             if gold_ok:
                 so = np.array(gold["spectrum"])
                 m = min(len(s), len(so))

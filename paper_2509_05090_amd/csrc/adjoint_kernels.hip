@@ -69,7 +69,67 @@ __global__ void copyltu_kernel(const double* in, double* out, int k) {
   }
 }
 
-// Column j of R^{-1}: back substitution.
+// Column j of R^{-1} diag(sgn), one wave per column, k <= 64 S: x = R^{-1} e_j
+// lives in registers (lane L holds rows L, L + 64, ...) and is found by
+// column back substitution, x_i <- x_i / R_ii then x_l -= R_li x_i for
+// l < i, over i = j, ..., 0.  The columns of R are read CH at a time, all
+// loads of a chunk in flight together; x_i reaches the wave by readlane.
+// Only the upper triangle of R is read (the strict lower part may hold
+// anything, e.g. Householder vectors).
+template <int S>
+__global__ __launch_bounds__(256) void tri_inv_upper_wave_kernel(const double* __restrict__ R,
+                                                                 int ldr, int k,
+                                                                 const double* __restrict__ sgn,
+                                                                 double* __restrict__ out) {
+  constexpr int CH = 16;
+  const int lane = threadIdx.x & 63;
+  const int j = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (j >= k) return;  // whole wave
+  double x[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) x[s] = s * 64 + lane == j ? 1.0 : 0.0;
+  for (int i0 = j / CH * CH; i0 >= 0; i0 -= CH) {
+    double r[CH][S], dinv[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int i = i0 + c;
+      const bool live = i <= j;
+      dinv[c] = live ? 1.0 / R[(int64_t)i * ldr + i] : 0.0;
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int row = s * 64 + lane;
+        r[c][s] = live && row < i ? R[(int64_t)row * ldr + i] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int c = CH - 1; c >= 0; --c) {
+      const int i = i0 + c;
+      if (i > j) continue;  // uniform
+      double xv = x[0];
+#pragma unroll
+      for (int s = 1; s < S; ++s)
+        if ((i >> 6) == s) xv = x[s];
+      const unsigned long long bits = __builtin_bit_cast(unsigned long long, xv);
+      const unsigned lo = __builtin_amdgcn_readlane((unsigned)bits, i & 63);
+      const unsigned hi = __builtin_amdgcn_readlane((unsigned)(bits >> 32), i & 63);
+      const double xi =
+          __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo) * dinv[c];
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int row = s * 64 + lane;
+        x[s] = row == i ? xi : fma(-r[c][s], xi, x[s]);  // r = 0 for rows >= i
+      }
+    }
+  }
+  const double sj = sgn ? sgn[j] : 1.0;
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int row = s * 64 + lane;
+    if (row < k) out[(int64_t)row * k + j] = row <= j ? x[s] * sj : 0.0;
+  }
+}
+
+// Column j of R^{-1}: back substitution, one thread per column (any k).
 __global__ void tri_inv_upper_kernel(const double* __restrict__ R, int ldr, int k,
                                      const double* __restrict__ sgn, double* __restrict__ out) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -326,7 +386,15 @@ void launch_copyltu(hipStream_t s, const double* in, double* out, int k) {
 
 void launch_tri_inv_upper(hipStream_t s, const double* R, int ldr, int k, const double* sgn,
                           double* out) {
-  tri_inv_upper_kernel<<<(unsigned)cdiv(k, 64), 64, 0, s>>>(R, ldr, k, sgn, out);
+  if (k <= 0) return;
+  const unsigned wg = (unsigned)cdiv(k, 4);
+  switch (cdiv(k, 64)) {
+    case 1: tri_inv_upper_wave_kernel<1><<<wg, 256, 0, s>>>(R, ldr, k, sgn, out); break;
+    case 2: tri_inv_upper_wave_kernel<2><<<wg, 256, 0, s>>>(R, ldr, k, sgn, out); break;
+    case 3: tri_inv_upper_wave_kernel<3><<<wg, 256, 0, s>>>(R, ldr, k, sgn, out); break;
+    case 4: tri_inv_upper_wave_kernel<4><<<wg, 256, 0, s>>>(R, ldr, k, sgn, out); break;
+    default: tri_inv_upper_kernel<<<(unsigned)cdiv(k, 64), 64, 0, s>>>(R, ldr, k, sgn, out);
+  }
   CTM_LAUNCHED();
 }
 

@@ -304,11 +304,19 @@ __global__ __launch_bounds__(RED_THREADS) void splitk_reduce(const Acc* __restri
                                                           int N, TC* C, int64_t ldc, double alpha,
                                                           double beta, double* sumsq) {
   const int64_t mn = (int64_t)M * N;
+  constexpr int SB = 8;  // partials loaded per batch (summed in order, s = 0, 1, ...)
   double ss = 0.0;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < mn;
        idx += (int64_t)gridDim.x * blockDim.x) {
     double v = 0.0;
-    for (int s = 0; s < S; ++s) v += (double)W[s * mn + idx];
+    for (int s0 = 0; s0 < S; s0 += SB) {
+      Acc p[SB];
+#pragma unroll
+      for (int j = 0; j < SB; ++j) p[j] = s0 + j < S ? W[(int64_t)(s0 + j) * mn + idx] : Acc(0);
+#pragma unroll
+      for (int j = 0; j < SB; ++j)
+        if (s0 + j < S) v += (double)p[j];
+    }
     const int64_t row = idx / N, col = idx % N;
     TC* dst = C + row * ldc + col;
     v *= alpha;
@@ -378,7 +386,10 @@ bool vec_ok(const Operand& o, size_t es) {
 template <typename Acc>
 void launch_reduce(DType out, const Acc* W, int S, int M, int N, void* C, int64_t ldc,
                    double alpha, double beta, double* sumsq, hipStream_t s) {
-  const int blocks = sumsq_blocks(M, N);
+  // with norm partials the block count is sumsq_blocks(); without, one
+  // element per thread
+  const int blocks = sumsq ? sumsq_blocks(M, N)
+                           : (int)std::min<int64_t>(65536, cdiv((int64_t)M * N, RED_THREADS));
   switch (out) {
     case DType::F64:
       splitk_reduce<Acc, double><<<blocks, RED_THREADS, 0, s>>>(W, S, M, N, (double*)C, ldc, alpha,

@@ -124,11 +124,15 @@ def test_gemm_two_level_batch(prec):
                                                   (3, 4, 256, 64, 64, True, False),
                                                   (4, 3, 100, 20, 50, False, True),
                                                   (2, 5, 17, 64, 3, False, False),
-                                                  (3, 2, 40, 9, 64, True, True)])
+                                                  (3, 2, 40, 9, 64, True, True),
+                                                  (1, 5, 200, 144, 36, False, False),
+                                                  (2, 3, 70, 100, 30, True, False)])
 def test_gemm_small_batches(prec, nb0, nb1, M, N, K, ta, tb):
-    """Batched products with K, N <= 64 and A shared across the second batch
+    """Batched products with small K and A shared across the second batch
     index (the pair contractions of the enlarged corner), several row tiles
-    of A, both operand layouts; C[b0][b1] lives in a padded row layout."""
+    of A, both operand layouts; C[b0][b1] lives in a padded row layout.
+    K, N <= 64 takes the small-batch kernel, the N > 64 cases the general
+    batched one."""
     r = _rng(nb0 * 1009 + nb1 * 101 + M + N + K + prec + 2 * ta + tb)
     A = r.standard_normal((nb0,) + ((K, M) if ta else (M, K)))
     B = r.standard_normal((nb1,) + ((N, K) if tb else (K, N)))
