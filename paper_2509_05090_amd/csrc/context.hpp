@@ -28,6 +28,10 @@ using ctm::Scratch;
 struct ctm_ctx {
   ctm_config cfg{};
   hipStream_t stream = nullptr;
+  // second stream of the projector (the explicit Q1 is formed there while
+  // the basis matrix is factored on `stream`), joined by ev_fork / ev_join
+  hipStream_t stream2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   std::string err;
   bool poisoned = false;
   int d = 0, D = 0, D2 = 0, chi = 0;
@@ -42,7 +46,7 @@ struct ctm_ctx {
   double* Anext = nullptr;  // site tensor under check by ctm_update_tensor
   double *C = nullptr, *T = nullptr, *Cn = nullptr, *Tn = nullptr, *P = nullptr;
   // FP64 work
-  double *M = nullptr, *Q = nullptr, *Cp = nullptr, *Tp = nullptr, *Xs = nullptr, *Xq = nullptr;
+  double *M = nullptr, *MP = nullptr, *Q = nullptr, *Cp = nullptr, *Tp = nullptr, *Xs = nullptr, *Xq = nullptr;
   double *sgn = nullptr, *sumsq = nullptr, *dev_small = nullptr;
   int* flag = nullptr;
   // Intermediates; allocated with 8-byte elements so that they hold any precision.
@@ -52,6 +56,7 @@ struct ctm_ctx {
   double *XO = nullptr, *EO = nullptr, *Cr2 = nullptr, *Cr4 = nullptr, *Cr5 = nullptr;
   double *rho_raw = nullptr, *h_dev = nullptr, *e_out = nullptr;
   QrWork qr;
+  QrWork qr2;  // chi x chi factorizations (the basis of the QR projector)
   ctm::EvdWork evd;  // eigendecomposition projector (CTM_PROJ_EVD only)
   Scratch ws;
   ctm::GradBuffers* grad = nullptr;  // adjoint workspace, allocated by the first ctm_grad
@@ -96,6 +101,12 @@ struct ctm_ctx {
 
   ~ctm_ctx() {
     if (stream) (void)hipStreamSynchronize(stream);
+    if (stream2) {
+      (void)hipStreamSynchronize(stream2);
+      (void)hipStreamDestroy(stream2);
+    }
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
     ctm::free_grad(grad);
     for (hipEvent_t e : event_pool) (void)hipEventDestroy(e);
     for (void* p : allocations) (void)hipFree(p);

@@ -179,19 +179,26 @@ void enlarged_corner(ctm_ctx* c, DType e) {
        0.0, c->ws);
 }
 
-// Gram-Schmidt basis of the columns of the k x k matrix X (QR with a
-// positive diagonal of R), into Qx.  X is overwritten.
-void gram_schmidt_small(ctm_ctx* c, double* X, int k, double* Qx) {
+// Gram-Schmidt basis of the columns of the k x k matrix X (leading
+// dimension ld; QR with a positive diagonal of R), into Qx (ld k).  X is
+// overwritten.  Uses the second QR workspace.
+void gram_schmidt_small(ctm_ctx* c, double* X, int ld, int k, double* Qx) {
   hipStream_t s = c->stream;
-  householder_qr(s, X, k, k, k, c->qr);
-  householder_form_q(s, c->qr, k, k, Qx, k);
-  launch_diag_signs(s, X, k, k, c->sgn);
+  householder_qr(s, X, ld, k, k, c->qr2);
+  householder_form_q(s, c->qr2, k, k, Qx, k);
+  launch_diag_signs(s, X, ld, k, c->sgn);
   launch_apply_signs(s, Qx, k, k, c->sgn, nullptr);
 }
 
 // Projector of the QR rule for the current Ct into c->Q (FP64, n x chi,
 // ld chi): thin QR of M = Ct P_prev, basis tied to P_prev (or to the start
 // projector when P_prev does not match n).  If update, P_prev <- Q.
+//
+// M and P_prev sit side by side in c->MP (n x 2 chi) and P_prev is carried
+// through the factorization's trailing updates, which leaves X = Q1^T P_prev
+// in the top chi rows of the carried block.  X no longer waits for Q1:
+// the explicit Q1 is formed on the second stream while X is factored on
+// this one, and the two meet before Q = Q1 gs(X).
 void qr_projector(ctm_ctx* c, DType e, bool update) {
   hipStream_t s = c->stream;
   const int chi = c->chi;
@@ -210,20 +217,27 @@ void qr_projector(ctm_ctx* c, DType e, bool update) {
   // enlarged corner and the next step): both operands of the product below
   // are then contiguous along its summed index.
   launch_cast_transpose(s, Pref, c->W, e, n, chi);
-  // 5. M = Ct P_prev (FP64 result), Q1 = thin QR factor
+  // 5. [M | P_prev], M = Ct P_prev (FP64 result); thin QR of M with P_prev
+  //    carried
+  const int ldmp = 2 * chi;
+  double* X = c->MP + chi;
   KernelEvents ev;
   gemm(s, e, n, chi, n, Operand{c->Ct, n, false}, Operand{c->W, n, true},
-       Output{c->M, chi, DType::F64}, 1, 1, 1.0, 0.0, c->ws, 0, nullptr,
+       Output{c->MP, ldmp, DType::F64}, 1, 1, 1.0, 0.0, c->ws, 0, nullptr,
        big_gemm_events(c, ev, n, chi, n));
-  householder_qr(s, c->M, chi, n, chi, c->qr);
-  householder_form_q(s, c->qr, n, chi, c->Q, chi);
-  // basis: Q = Q1 gs(Q1^T P_prev)
-  gemm(s, DType::F64, chi, chi, n, Operand{c->Q, chi, true}, Operand{Pref, chi, false},
-       Output{c->Xs, chi, DType::F64}, 1, 1, 1.0, 0.0, c->ws);
-  gram_schmidt_small(c, c->Xs, chi, c->Xq);
-  gemm(s, DType::F64, n, chi, chi, Operand{c->Q, chi, false}, Operand{c->Xq, chi, false},
-       Output{c->M, chi, DType::F64}, 1, 1, 1.0, 0.0, c->ws);
-  std::swap(c->Q, c->M);
+  CTM_HIP(hipMemcpy2DAsync(X, (size_t)ldmp * sizeof(double), Pref, (size_t)chi * sizeof(double),
+                           (size_t)chi * sizeof(double), (size_t)n, hipMemcpyDeviceToDevice, s));
+  householder_qr(s, c->MP, ldmp, n, chi, c->qr, ldmp);
+  // Q1 into M on the second stream
+  CTM_HIP(hipEventRecord(c->ev_fork, s));
+  CTM_HIP(hipStreamWaitEvent(c->stream2, c->ev_fork, 0));
+  householder_form_q(c->stream2, c->qr, n, chi, c->M, chi);
+  CTM_HIP(hipEventRecord(c->ev_join, c->stream2));
+  // basis: Q = Q1 gs(X), X = Q1^T P_prev
+  gram_schmidt_small(c, X, ldmp, chi, c->Xq);
+  CTM_HIP(hipStreamWaitEvent(s, c->ev_join, 0));
+  gemm(s, DType::F64, n, chi, chi, Operand{c->M, chi, false}, Operand{c->Xq, chi, false},
+       Output{c->Q, chi, DType::F64}, 1, 1, 1.0, 0.0, c->ws);
   if (update)
     CTM_HIP(hipMemcpyAsync(c->P, c->Q, (size_t)n * chi * sizeof(double), hipMemcpyDeviceToDevice, s));
 }
@@ -453,6 +467,7 @@ void allocate(ctm_ctx* c) {
   c->Tn = c->allocd(chi * D2 * chi);
   c->P = c->allocd(nmax * chi);
   c->M = c->allocd(nmax * chi);
+  c->MP = c->allocd(nmax * 2 * chi);
   c->Q = c->allocd(nmax * chi);
   c->Cp = c->allocd(chi * chi);
   c->Xs = c->allocd(chi * chi);
@@ -475,6 +490,11 @@ void allocate(ctm_ctx* c) {
   c->V2 = c->allocd(nmax * chi);
   c->qr = qr_work_carve(c->stream, c->alloc(qr_work_bytes((int)nmax, (int)chi)), (int)nmax,
                         (int)chi);
+  c->qr2 = qr_work_carve(c->stream, c->alloc(qr_work_bytes((int)chi, (int)chi)), (int)chi,
+                         (int)chi);
+  CTM_HIP(hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking));
+  CTM_HIP(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+  CTM_HIP(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
   if (c->cfg.proj == CTM_PROJ_EVD)
     c->evd = evd_work_carve(c->alloc(evd_work_bytes((int)nmax, (int)chi)), (int)nmax, (int)chi);
   size_t wsb = std::max(gemm_scratch_bytes(DType::F64, (int)nmax, (int)chi),

@@ -583,8 +583,10 @@ QrPanel qr_panel_plan(int n, int k, int j0) {
   return p;
 }
 
-void householder_qr(hipStream_t s, double* M, int ld, int n, int k, QrWork& w) {
+void householder_qr(hipStream_t s, double* M, int ld, int n, int k, QrWork& w, int kx) {
+  if (kx < 0) kx = k;
   if (n < k || k < 1) throw std::invalid_argument("householder_qr: needs n >= k >= 1");
+  if (kx < k || ld < kx) throw std::invalid_argument("householder_qr: needs ld >= kx >= k");
   if (n > QR_MAX_ROWS) throw std::invalid_argument("householder_qr: n > 32768");
   if (n > w.n || k != w.k) throw std::invalid_argument("householder_qr: workspace shape mismatch");
   const int nb = nb_of(n);
@@ -595,9 +597,9 @@ void householder_qr(hipStream_t s, double* M, int ld, int n, int k, QrWork& w) {
       throw std::logic_error("householder_qr: bad panel plan");
     launch_panel(s, p, M, ld, n, w, panel);
     const int c0 = j0 + p.w;
-    if (c0 >= k) continue;
-    launch_apply(s, false, true, p, M, ld, c0, k, n, w, panel);
-    if (p.L > 1) launch_apply(s, true, true, p, M, ld, c0, k, n, w, panel);
+    if (c0 >= kx) continue;
+    launch_apply(s, false, true, p, M, ld, c0, kx, n, w, panel);
+    if (p.L > 1) launch_apply(s, true, true, p, M, ld, c0, kx, n, w, panel);
   }
 }
 

@@ -54,7 +54,11 @@ QrPanel qr_panel_plan(int n, int k, int j0);
 // R in the upper triangle of the first k rows (zeros below it within the
 // first k rows); the reflectors go to w.  R's diagonal signs follow the
 // stacked factorization, not LAPACK's convention.
-void householder_qr(hipStream_t s, double* M, int ld, int n, int k, QrWork& w);
+// With kx > k, columns [k, kx) of M are carried along: every panel's
+// trailing update applies to them too, so that they end up as Q^T B for
+// their input B (Q the full n x n orthogonal factor); their first k rows
+// are then Q1^T B, Q1 = the thin factor of householder_form_q().
+void householder_qr(hipStream_t s, double* M, int ld, int n, int k, QrWork& w, int kx = -1);
 
 // Explicit Q (n x k, leading dimension ldq) of the last householder_qr().
 void householder_form_q(hipStream_t s, const QrWork& w, int n, int k, double* Q, int ldq);
