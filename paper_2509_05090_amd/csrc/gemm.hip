@@ -456,82 +456,83 @@ template <typename E, int KS, int NT>
 __global__ __launch_bounds__(256) void small_batch_kernel(SmallBatchArgs g) {
   using MF = Mfma<E>;
   using accv = typename MF::accv;
-  constexpr int KSTEP = 4 * MF::KPL;  // k per MFMA
+  constexpr int KPL = MF::KPL;
+  constexpr int KSTEP = 4 * KPL;      // k per MFMA
   constexpr int KPAD = KS * KSTEP;    // k range held in LDS (zero beyond K)
-  constexpr int NP = NT * 16;         // columns held in LDS (zero beyond N)
   extern __shared__ __attribute__((aligned(16))) unsigned char sb_lds[];
-  E* As = (E*)sb_lds;                 // [mt][kp]
-  E* Bs = As + (int64_t)g.mt * g.kp;  // [NP][kp]
+  E* As = (E*)sb_lds;  // [mt][kp]
 
   const int b0 = blockIdx.x / g.mtiles, m0 = (blockIdx.x % g.mtiles) * g.mt;
   const int rows = min(g.mt, g.M - m0);
   const E* __restrict__ A = (const E*)g.A + (int64_t)b0 * g.sA0;
 
-  // A tile [m][k], zero beyond the data; loads issued in batches of LB per
-  // thread before their LDS stores.
-  constexpr int LB = 16;
-  const int atotal = g.mt * KPAD;
-  for (int base = 0; base < atotal; base += 256 * LB) {
-    E v[LB];
+  // A tile [m][k], zero beyond the data.  The source is walked in its own
+  // storage order (k-major when transposed) with the (outer, inner) position
+  // advanced incrementally; loads are issued in batches of LB per thread
+  // before their LDS stores.
+  {
+    constexpr int LB = 16;
+    const int outer = g.at ? KPAD : g.mt, inner = g.at ? g.mt : KPAD;
+    const int so = 256 / inner, si = 256 % inner;
+    int o = threadIdx.x / inner, in = threadIdx.x % inner;
+    while (o < outer) {
+      E v[LB];
+      int om[LB], im[LB];
 #pragma unroll
-    for (int j = 0; j < LB; ++j) {
-      const int i = base + j * 256 + threadIdx.x;
-      const int m = g.at ? i % g.mt : i / KPAD, k = g.at ? i / g.mt : i % KPAD;
-      v[j] = zero_of<E>();
-      if (i < atotal && m < rows && k < g.K)
-        v[j] = g.at ? A[(int64_t)k * g.lda + m0 + m] : A[(int64_t)(m0 + m) * g.lda + k];
-    }
+      for (int j = 0; j < LB; ++j) {
+        om[j] = o;
+        im[j] = in;
+        const int m = g.at ? in : o, k = g.at ? o : in;
+        v[j] = zero_of<E>();
+        if (o < outer && m < rows && k < g.K)
+          v[j] = g.at ? A[(int64_t)k * g.lda + m0 + m] : A[(int64_t)(m0 + m) * g.lda + k];
+        in += si;
+        o += so;
+        if (in >= inner) {
+          in -= inner;
+          ++o;
+        }
+      }
 #pragma unroll
-    for (int j = 0; j < LB; ++j) {
-      const int i = base + j * 256 + threadIdx.x;
-      const int m = g.at ? i % g.mt : i / KPAD, k = g.at ? i / g.mt : i % KPAD;
-      if (i < atotal) As[m * g.kp + k] = v[j];
+      for (int j = 0; j < LB; ++j) {
+        const int m = g.at ? im[j] : om[j], k = g.at ? om[j] : im[j];
+        if (om[j] < outer) As[m * g.kp + k] = v[j];
+      }
     }
   }
+  __syncthreads();
 
+  // Each wavefront takes its own batches b1 = first + wid + 4 i and sweeps
+  // every row tile of the A tile with them: no barrier after the A tile.
+  // The B fragments come straight from memory, one batch ahead of use.
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int r16 = lane & 15, grp = lane >> 4;
-  const int b1beg = blockIdx.y * g.group, b1end = min(g.nb1, b1beg + g.group);
-  // B[b1] as [n][k], held in registers one batch ahead of its use
-  constexpr int BPT = (NP * KPAD + 255) / 256;
-  E rb[BPT];
-  auto load_b = [&](int b1) {
+  const int b1first = blockIdx.y * g.group, b1end = min(g.nb1, b1first + g.group);
+  E bf[NT][KS][KPL], bn[NT][KS][KPL];
+  auto load_b = [&](int b1, E (&dst)[NT][KS][KPL]) {
     const E* __restrict__ B = (const E*)g.B + (int64_t)b1 * g.sB1;
-#pragma unroll
-    for (int j = 0; j < BPT; ++j) {
-      const int i = j * 256 + threadIdx.x;
-      const int n = g.bt ? i / KPAD : i % NP, k = g.bt ? i % KPAD : i / NP;
-      rb[j] = zero_of<E>();
-      if (i < NP * KPAD && n < g.N && k < g.K)
-        rb[j] = g.bt ? B[(int64_t)n * g.ldb + k] : B[(int64_t)k * g.ldb + n];
-    }
-  };
-  if (b1beg < b1end) load_b(b1beg);
-  for (int b1 = b1beg; b1 < b1end; ++b1) {
-    __syncthreads();  // previous B no longer read (and A stored, first time)
-#pragma unroll
-    for (int j = 0; j < BPT; ++j) {
-      const int i = j * 256 + threadIdx.x;
-      const int n = g.bt ? i / KPAD : i % NP, k = g.bt ? i % KPAD : i / NP;
-      if (i < NP * KPAD) Bs[n * g.kp + k] = rb[j];
-    }
-    __syncthreads();
-    if (b1 + 1 < b1end) load_b(b1 + 1);
-    // B fragments of this batch, shared by all row tiles of the wavefront
-    E bf[NT][KS][MF::KPL];
 #pragma unroll
     for (int t = 0; t < NT; ++t)
 #pragma unroll
       for (int s = 0; s < KS; ++s)
-        __builtin_memcpy(&bf[t][s][0], &Bs[(t * 16 + r16) * g.kp + s * KSTEP + grp * MF::KPL],
-                         MF::KPL * sizeof(E));
+#pragma unroll
+        for (int u = 0; u < KPL; ++u) {
+          const int n = t * 16 + r16, k = s * KSTEP + grp * KPL + u;
+          dst[t][s][u] = zero_of<E>();
+          if (n < g.N && k < g.K) dst[t][s][u] = g.bt ? B[(int64_t)n * g.ldb + k] : B[(int64_t)k * g.ldb + n];
+        }
+  };
+  int b1 = b1first + wid;
+  if (b1 < b1end) load_b(b1, bf);
+  for (; b1 < b1end; b1 += 4) {
+    if (b1 + 4 < b1end) load_b(b1 + 4, bn);
     E* __restrict__ C = (E*)g.C + (int64_t)b0 * g.sC0 + (int64_t)b1 * g.sC1;
-    for (int tm = wid; tm * 16 < rows; tm += 4) {
-      E af[KS][MF::KPL];
+    for (int tm = 0; tm * 16 < rows; ++tm) {
+      E af[KS][KPL];
 #pragma unroll
       for (int s = 0; s < KS; ++s)
-        __builtin_memcpy(&af[s][0], &As[(tm * 16 + r16) * g.kp + s * KSTEP + grp * MF::KPL],
-                         MF::KPL * sizeof(E));
+        __builtin_memcpy(&af[s][0], &As[(tm * 16 + r16) * g.kp + s * KSTEP + grp * KPL],
+                         KPL * sizeof(E));
       accv acc[NT];
 #pragma unroll
       for (int t = 0; t < NT; ++t) acc[t] = accv{0, 0, 0, 0};
@@ -550,6 +551,12 @@ __global__ __launch_bounds__(256) void small_batch_kernel(SmallBatchArgs g) {
         }
       }
     }
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int s = 0; s < KS; ++s)
+#pragma unroll
+        for (int u = 0; u < KPL; ++u) bf[t][s][u] = bn[t][s][u];
   }
 }
 
@@ -584,25 +591,25 @@ bool small_batch(hipStream_t s, DType e, int M, int N, int K, const Operand& A, 
   }
   const int kpad = ks * kstep;
   const int kp = kpad + 16 / es;  // 16 bytes of row padding
-  const int np = nt * 16;
-  const int64_t bbytes = (int64_t)np * kp * es;
-  const int64_t mt_fit = (SB_LDS - bbytes) / ((int64_t)kp * es) / 16 * 16;
+  const int64_t mt_fit = SB_LDS / ((int64_t)kp * es) / 16 * 16;
   if (mt_fit < 16) return false;
   SmallBatchArgs g{};
-  g.mt = (int)std::min<int64_t>(mt_fit, cdiv(M, 16) * 16);
-  g.mtiles = (int)cdiv(M, g.mt);
+  // row tiles of (nearly) equal height
+  g.mtiles = (int)cdiv(M, mt_fit);
+  g.mt = (int)(cdiv(cdiv(M, g.mtiles), 16) * 16);
   g.M = M; g.N = N; g.K = K;
   g.A = A.p; g.lda = A.ld; g.sA0 = A.s0; g.at = A.trans;
   g.B = B.p; g.ldb = B.ld; g.sB1 = B.s1; g.bt = B.trans;
   g.C = C.p; g.ldc = C.ld; g.sC0 = C.s0; g.sC1 = C.s1;
   g.nb0 = nb0; g.nb1 = nb1;
   g.kp = kp;
-  // about four workgroups per compute unit, each reusing its A tile over
-  // `group` batches of B
+  // each workgroup reuses its A tile over `group` batches of B, a multiple
+  // of the four wavefronts (one batch each at a time), sized for about four
+  // thousand wavefronts' worth of batches in flight
   const int64_t base = (int64_t)nb0 * g.mtiles;
-  g.group = (int)std::max<int64_t>(1, std::min<int64_t>(nb1, cdiv(base * nb1, 1024)));
+  g.group = (int)std::min<int64_t>(4 * cdiv(nb1, 4), 4 * std::max<int64_t>(1, cdiv(base * nb1, 4096)));
   const dim3 grid((unsigned)base, (unsigned)cdiv(nb1, g.group));
-  const size_t lds = (size_t)(g.mt + np) * kp * es;
+  const size_t lds = (size_t)g.mt * kp * es;
 #define CTM_SB(T, KS_, NT_) small_batch_kernel<T, KS_, NT_><<<grid, 256, lds, s>>>(g)
   // (ks, nt) is exactly one of the instances below
   if (e == DType::BF16) {
