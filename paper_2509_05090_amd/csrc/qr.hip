@@ -176,23 +176,49 @@ __device__ __forceinline__ void qr_column(double (&a)[TR][NBT / 16], double (&sc
 #pragma unroll
   for (int u = 0; u < QW; ++u) sigma += sh.red[par][u][k];
   const double x0 = sh.piv[par][k];
-  double beta, tau, scale;
+  // beta, tau, the reflector's scale 1 / (x0 - beta) and tau scale = -1 / beta.
+  // With y = 1 / ||(x0, x)||: tau = 1 + |x0| y, tau scale = sign(x0) y and
+  // scale = sign(x0) / (|x0| + ||(x0, x)||); y and the reciprocal come from
+  // the hardware estimates refined by two Newton steps each.  Outside a safe
+  // exponent range (a uniform branch) the library square root and divisions.
+  double beta, tau, scale, ts;
+  const double s2 = fma(x0, x0, sigma);
   if (sigma == 0.0) {
     tau = 2.0;
     beta = -x0;
     scale = 0.0;
+    ts = 0.0;
+  } else if (s2 >= 0x1p-960 && s2 <= 0x1p960) {
+    double y = __builtin_amdgcn_rsq(s2);
+    double e = fma(-s2 * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    e = fma(-s2 * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    const double nrm = s2 * y, ax = fabs(x0);
+    const double d = ax + nrm;
+    double r = __builtin_amdgcn_rcp(d);
+    e = fma(-d, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-d, r, 1.0);
+    r = fma(r, e, r);
+    const bool pos = x0 >= 0.0;
+    beta = pos ? -nrm : nrm;
+    tau = fma(ax, y, 1.0);
+    scale = pos ? r : -r;
+    ts = pos ? y : -y;
   } else {
-    const double nrm = sqrt(x0 * x0 + sigma);
+    const double nrm = sqrt(s2);
     beta = x0 >= 0.0 ? -nrm : nrm;
     tau = (beta - x0) / beta;
     scale = 1.0 / (x0 - beta);
+    ts = tau * scale;
   }
   if (i == (k & 15)) sc[H] = scale;
   double wv[SL], uv[SL];
 #pragma unroll
   for (int h = 0; h < SL; ++h) {
     wv[h] = p[h] + scale * f[h];  // v . a_c
-    uv[h] = (i + 16 * h > k) ? tau * scale * wv[h] : 0.0;
+    uv[h] = (i + 16 * h > k) ? ts * wv[h] : 0.0;
   }
   if (v == 0 && g == 0) {
 #pragma unroll
@@ -203,11 +229,12 @@ __device__ __forceinline__ void qr_column(double (&a)[TR][NBT / 16], double (&sc
     }
     if (i == 0) sh.tau[k] = tau;
   }
-  // 4. rows below the pivot (x is zero at and above it)
+  // 4. rows below the pivot (x is zero at and above it); slots before H
+  //    hold finished columns only
 #pragma unroll
   for (int t = 0; t < TR; ++t)
 #pragma unroll
-    for (int h = 0; h < SL; ++h) a[t][h] -= x[t] * uv[h];
+    for (int h = H; h < SL; ++h) a[t][h] -= x[t] * uv[h];
 }
 
 // Householder QR of a block of m rows x w columns held in registers (layout
