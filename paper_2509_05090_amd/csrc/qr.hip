@@ -1,25 +1,24 @@
 // Blocked Householder QR (FP64) for tall-skinny matrices, with each panel
 // factored as a tall-skinny QR (TSQR) over row blocks.
 //
-// Panel kernel: one workgroup of 256 threads (one wavefront per SIMD) per
-// leaf holds its row block of the panel in registers, RPT rows per thread,
-// and runs the Householder column loop.  The register window rotates: the
-// columns are processed four at a time at fixed register positions 0..3, and
-// after each group the finished columns (reflectors below the diagonal, R on
-// and above it) are written out and the window shifts by four.  Per column a
-// single reduction gives, for the rows below the pivot, the column's squared
-// norm and its inner products with the later columns; it is a
-// reduce-scatter across the 64 lanes of a wavefront (permlane swaps across
-// the 32- and 16-lane halves, DPP within rows of 16), then one LDS pass
-// across the four wavefronts.  The reflector follows LAPACK's dlarfg
-// (beta = -sign(x0) ||x||); an already-zero column gets the reflector
-// I - 2 e e^T, which keeps every reflector's tau in [1, 2].  The compact WY
-// factor comes from the Gram matrix of the reflectors (Joffrain, Low,
-// Quintana-Orti, van de Geijn, van Zee, ACM TOMS 32 (2006)):
-// T^{-1} = diag(1/tau) + strictly-upper(Y^T Y), the Gram matrix on the
-// matrix cores, the triangular inverse by one wavefront.  Leaves write their
-// triangular factors to a stack; the last leaf to finish (atomic counter,
-// no waiting) factors the stack in the same way.
+// Panel kernel: one workgroup of four wavefronts (one per SIMD) per leaf
+// holds its row block of the panel in registers and runs the Householder
+// column loop.  In each wavefront, lane 16 g + i holds column i (and i + 16)
+// of the rows in row group g.  Per column, the pivot column below the
+// diagonal goes to every lane of its row group through wavefront-private
+// LDS; each lane forms its partial inner products with its columns (which
+// give the column's squared norm and its products with the other columns),
+// sums them over the four row groups with permlane swaps and over the
+// wavefronts through one LDS pass, and applies the reflector to its rows.
+// The reflector follows LAPACK's dlarfg (beta = -sign(x0) ||x||); an
+// already-zero column gets the reflector I - 2 e e^T, which keeps every
+// reflector's tau in [1, 2].  The compact WY factor comes from the Gram
+// matrix of the reflectors (Joffrain, Low, Quintana-Orti, van de Geijn, van
+// Zee, ACM TOMS 32 (2006)): T^{-1} = diag(1/tau) + strictly-upper(Y^T Y),
+// the Gram matrix assembled from the same inner products, the triangular
+// inverse by one wavefront.  Leaves write their triangular factors to a
+// stack; the last leaf to finish (atomic counter, no waiting) factors the
+// stack in the same way.
 //
 // Apply kernel: B <- (I - Y op(T) Y^T) B on a range of columns, per leaf
 // (row block) or on the stacked rows, 16 columns and 16 wavefronts per
