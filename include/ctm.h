@@ -150,7 +150,11 @@ int ctm_energy(ctm_ctx *c, const double *h_host, double *e_host, double *rho_hos
  *    dE/dA = dE/dA|_env + sum_j (dF/dA)^T (J^T)^j dE/d(env), J the step's
  *    Jacobian; terms are added until one changes the cotangent of the
  *    double layer by less than tol relative to its norm (CTM_ENOTCONV after
- *    max_iter terms; the gradient is still written).
+ *    max_iter terms; the gradient is still written).  CTM_ESTATE (nothing
+ *    written) if one step changes the unit-norm corner by more than 1e-5:
+ *    where the corner spectrum comes in +-lambda pairs, C keeps turning
+ *    within their eigenspaces at convergence (T, P, the spectrum and the
+ *    energy converge), so the state is no fixed point; use mode k > 0.
  * gradA_dev: d*D^3 FP64 device buffer, receives the projection of dE/dA onto
  * the C3v-symmetric subspace.  e_host (nullable): E.  iters_host (nullable):
  * adjoint steps taken.  Allocates its workspace (about nine (chi D^2)^2 FP64

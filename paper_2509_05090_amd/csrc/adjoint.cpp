@@ -26,8 +26,10 @@
 // to zero: gauge rotations of the kept basis are marginal directions of the
 // step, and rounding leaves components along them that the energy does not
 // see.)
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <string>
 #include <vector>
 
 #include "adjoint_kernels.hpp"
@@ -435,6 +437,10 @@ void increment_norms(ctm_ctx* c, double* inc2, double* tot2) {
 
 }  // namespace
 
+// Largest change of the (unit-norm) corner under one step that mode 0
+// accepts as stationary.
+constexpr double kStationaryCorner = 1e-5;
+
 int do_grad(ctm_ctx* c, const double* h_host, int mode, double tol, int max_iter, double* gradA_dev,
             double* e_host, int* iters_host) {
   if (!h_host || !gradA_dev || mode < 0 || max_iter < 0)
@@ -457,6 +463,26 @@ int do_grad(ctm_ctx* c, const double* h_host, int mode, double tol, int max_iter
   bool converged = true;
   if (mode == 0) {
     tape_forward(c, c->C, c->T, c->P);
+    // The series assumes a fixed point element by element.  Where the corner
+    // spectrum has +-lambda pairs, C keeps turning within their
+    // two-dimensional eigenspaces while T, P, the spectrum and the energy
+    // converge; one step then changes C by O(max |C|) and the series does
+    // not converge.  Refuse such a state (the unrolled mode handles it).
+    {
+      std::vector<double> c0((size_t)x2), c1((size_t)x2);
+      CTM_HIP(hipMemcpyAsync(c0.data(), c->C, (size_t)x2 * sizeof(double), hipMemcpyDeviceToHost, s));
+      CTM_HIP(hipMemcpyAsync(c1.data(), b.tp.Cn, (size_t)x2 * sizeof(double), hipMemcpyDeviceToHost,
+                             s));
+      CTM_HIP(hipStreamSynchronize(s));
+      double dc = 0.0;
+      for (int64_t i = 0; i < x2; ++i) dc = std::max(dc, std::fabs(c1[i] - c0[i]));
+      if (!(dc <= kStationaryCorner)) {
+        c->err = "ctm_grad mode 0 needs a stationary environment, but one step changes the corner by " +
+                 std::to_string(dc) +
+                 " (the corner keeps turning within +-lambda pairs of its spectrum); use mode k > 0";
+        return CTM_ESTATE;
+      }
+    }
     energy_vjp(c, c->C, c->T, c->P, b.xC[0], b.xT[0], b.xP[0]);
     int cur = 0;
     converged = false;

@@ -157,6 +157,55 @@ def test_gradient_properties_and_finite_differences_c4():
     print(f"20 directions: max |<g,v> - FD| = {worst:.2e}")
 
 
+def test_fixed_point_mode_refuses_a_turning_corner():
+    """Kitaev workload (D=4, chi=64), converged: its corner spectrum comes in
+    +-lambda pairs and one more step turns C within their eigenspaces while T
+    and the projector stay put, so the state is no fixed point element by
+    element.  The fixed-point adjoint refuses it (CTM_ESTATE); the unrolled
+    gradient through 40 tracked steps matches central differences (h = 1e-6)
+    of converged energies along two seeded symmetric directions."""
+    w = ci.WORKLOADS["c2"]
+    A = ctm.symmetrize(torch.tensor(ci.raw_site_tensor(w), device=DEV))
+    G = torch.tensor(ci.start_matrix(w), device=DEV)
+    h = ci.site_energy_operator(w)
+    c = ctm.Context(A, G, w.chi)
+    _, _, ok = c.converge(1e-12, 6000, n_check=10)
+    assert ok
+    s = c.spectrum()
+    assert np.abs(s[0:40:2] - s[1:40:2]).max() < 1e-9
+    C0, T0, P0 = c.get_env()
+    c.step(1)
+    C1, T1, P1 = c.get_env()
+    dc, dt = (C1 - C0).abs().max().item(), (T1 - T0).abs().max().item()
+    print(f"c2: one step changes C by {dc:.2e}, T by {dt:.2e}")
+    assert dc > 1e-3 and dt < 1e-6
+    c.set_env(C0, T0, P0)
+    with pytest.raises(ctm.CtmError) as err:
+        c.grad(h, mode=0)
+    assert err.value.code == ctm.CTM_ESTATE
+    g, e, iters, okg = c.grad(h, mode=40)
+    c.close()
+    assert okg and iters == 40
+
+    def converged_energy(At):
+        with ctm.Context(At, G, w.chi) as cc:
+            cc.set_env(C0, T0, P0)
+            _, _, okc = cc.converge(1e-13, 8000, n_check=10)
+            assert okc
+            en, _ = cc.energy(h)
+        return en
+
+    gn = g.cpu().numpy()
+    for seed in ci.DIRECTION_SEEDS[:2]:
+        v = oracle.symmetrize(ci.direction(w, seed))
+        v /= np.linalg.norm(v)
+        vt = torch.tensor(v, device=DEV)
+        fd = (converged_energy(A + 1e-6 * vt) - converged_energy(A - 1e-6 * vt)) / 2e-6
+        dot = float(np.sum(gn * v))
+        print(f"direction {seed}: <g,v> = {dot:.10f}, FD = {fd:.10f}")
+        assert abs(dot - fd) <= 1e-7 * max(1.0, abs(fd))
+
+
 def test_grad_needs_truncated_environment():
     w = ci.Workload("t", 2, 2, 16, 1, 2)
     A = ctm.symmetrize(torch.tensor(ci.raw_site_tensor(w), device=DEV))
