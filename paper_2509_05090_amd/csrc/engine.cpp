@@ -21,9 +21,11 @@
 //   6. Gm = Ct . Q                                    (n x chi, k = n)
 //   7. C' = Q^T . Gm, then (C' + C'^T)/2 / ||.||_F     (chi x chi, k = n)
 //   8. V2 = V . Q                                     (n x chi, k = n)
-//   9. V3[alpha][(k,l)][nu] = sum_m a[k][l][m] V2[(alpha,m)][nu]
-//        chi_c products of (D2*D2 x chi), k = D2
-//  10. T' = Q^T . V3 (V3 read as n x (D2 chi)), then / ||.||_F
+//   9. V3[alpha][(k,l)][nu] = sum_m a[k][l][m] V2[(alpha,m)][nu], stored
+//        transposed as [(l,nu)][(alpha,k)] (chi_c D2 batches of chi x D2,
+//        k = D2)
+//  10. T' = Q^T . V3 (V3 read as n x (D2 chi), from its transposed store),
+//        then / ||.||_F
 //
 // Steps 1-4 and 6-10 run in the context's arithmetic (FP64, or FP32/BF16
 // matrix cores with FP32 accumulation); the QR, sign gauge and norms are
@@ -302,14 +304,18 @@ void step_once(ctm_ctx* c) {
   gemm(s, e, (int)n, xn, (int)n, Operand{c->V, n, false}, Operand{QT, n, true},
        Output{c->V2, xn, e}, 1, 1, 1.0, 0.0, c->ws, 0, nullptr,
        big_gemm_events(c, ev2, n, xn, n));
-  // 9. V3[alpha][(k,l)][nu] into the Ct buffer (Ct is no longer needed)
+  // 9. V3 stored transposed, V3t[(l,nu)][(alpha,k)] = sum_m a[k][l][m] V2[(alpha,m)][nu],
+  //    into the Ct buffer (Ct is no longer needed): batches (alpha, l) of
+  //    xn x D2 x D2 products, A[alpha](nu, m) = V2[alpha][m][nu],
+  //    B[l](m, k) = a[k][l][m]
   const void* aE = e == DType::F64 ? (const void*)c->a : c->aE;
-  void* V3 = c->Ct;
-  gemm(s, e, D2 * D2, xn, D2, Operand{aE, D2, false, 0}, Operand{c->V2, xn, false, (int64_t)D2 * xn},
-       Output{V3, xn, e, (int64_t)D2 * D2 * xn}, x, 1, 1.0, 0.0, c->ws);
-  // 10. T' = Q^T V3, normalized
+  void* V3t = c->Ct;
+  gemm(s, e, xn, D2, D2, Operand{c->V2, xn, true, (int64_t)D2 * xn, 0},
+       Operand{aE, (int64_t)D2 * D2, true, 0, D2}, Output{V3t, n, e, D2, (int64_t)xn * n}, x, D2,
+       1.0, 0.0, c->ws);
+  // 10. T'[mu][(l,nu)] = sum_(alpha,k) Q[(alpha,k)][mu] V3t[(l,nu)][(alpha,k)], normalized
   const int64_t tn = (int64_t)xn * D2 * xn;
-  gemm(s, e, xn, D2 * xn, (int)n, Operand{QT, n, false}, Operand{V3, (int64_t)D2 * xn, false},
+  gemm(s, e, xn, D2 * xn, (int)n, Operand{QT, n, false}, Operand{V3t, n, true},
        Output{c->Tp, (int64_t)D2 * xn, DType::F64}, 1, 1, 1.0, 0.0, c->ws, 0, c->sumsq);
   launch_scale_by_norm(s, c->Tp, c->Tn, tn, c->sumsq, sumsq_blocks(xn, D2 * xn), c->flag);
   stage_end(c, CTM_STAGE_RENORM_T);
