@@ -277,9 +277,53 @@ __device__ __forceinline__ void local_qr(double (&a)[TR][NBT / 16], int m, int w
     const int r = idx / w, c = idx % w;
     Rd[(int64_t)r * ldr + c] = sh.R[r][c];
   }
-  // T = (diag(1/tau) + strictly-upper(G))^{-1}, by back substitution with
-  // one column of T per lane of wavefront 0.
-  if (tid < 64) {
+  // T = U^{-1}, U = diag(1/tau) + strictly-upper(G), zero outside w x w.
+  if constexpr (NBT == 32) {
+    // By 16 x 16 blocks: T11 = U11^{-1} and T22 = U22^{-1} by back
+    // substitution (one column per lane, wavefronts 0 and 1 at once), then
+    // T12 = -T11 (U12 T22), one element per thread.  The pivot-column
+    // staging area (free after the column loop) holds T11, T22 and U12 T22.
+    constexpr int HB = 16;
+    double* st = &sh.xs[0][0][0];
+    if (tid < 128) {
+      const int v = tid >> 6, j = tid & 63, o = HB * v;
+      if (j < HB) {
+        double tc[HB];
+#pragma unroll
+        for (int ii = HB - 1; ii >= 0; --ii) {
+          double s0 = ii == j ? 1.0 : 0.0, s1 = 0.0;
+#pragma unroll
+          for (int kk = ii + 1; kk < HB; ++kk) {
+            if ((kk - ii) & 1) s0 -= sh.G[o + ii][o + kk] * tc[kk];
+            else s1 -= sh.G[o + ii][o + kk] * tc[kk];
+          }
+          tc[ii] = (o + ii < w && o + j < w && ii <= j) ? sh.tau[o + ii] * (s0 + s1) : 0.0;
+        }
+#pragma unroll
+        for (int ii = 0; ii < HB; ++ii) {
+          st[v * HB * HB + ii * HB + j] = tc[ii];
+          Tout[(o + ii) * NBT + o + j] = tc[ii];
+          if (v == 1) Tout[(HB + ii) * NBT + j] = 0.0;  // lower-left block
+        }
+      }
+    }
+    __syncthreads();
+    const int r = tid >> 4, cc = tid & 15;  // 256 threads: one element of a 16 x 16 block
+    {
+      double x = 0.0;
+#pragma unroll
+      for (int k = 0; k < HB; ++k) x += sh.G[r][HB + k] * st[HB * HB + k * HB + cc];
+      st[2 * HB * HB + r * HB + cc] = x;  // U12 T22
+    }
+    __syncthreads();
+    {
+      double t12 = 0.0;
+#pragma unroll
+      for (int k = 0; k < HB; ++k) t12 -= st[r * HB + k] * st[2 * HB * HB + k * HB + cc];
+      Tout[r * NBT + HB + cc] = t12;
+    }
+  } else if (tid < 64) {
+    // one column of T per lane of wavefront 0, by back substitution
     const int j = tid;
     double tc[NBT];
 #pragma unroll
