@@ -192,16 +192,17 @@ void gram_schmidt_small(ctm_ctx* c, double* X, int ld, int k, double* Qx) {
   launch_apply_signs(s, Qx, k, k, c->sgn, nullptr);
 }
 
-// Projector of the QR rule for the current Ct into c->Q (FP64, n x chi,
-// ld chi): thin QR of M = Ct P_prev, basis tied to P_prev (or to the start
-// projector when P_prev does not match n).  If update, P_prev <- Q.
+// Projector of the QR rule for the current Ct (FP64, n x chi, ld chi): thin
+// QR of M = Ct P_prev, basis tied to P_prev (or to the start projector when
+// P_prev does not match n).  Written into c->P (the new P_prev) if update,
+// else into c->Q; returns where.
 //
 // M and P_prev sit side by side in c->MP (n x 2 chi) and P_prev is carried
 // through the factorization's trailing updates, which leaves X = Q1^T P_prev
 // in the top chi rows of the carried block.  X no longer waits for Q1:
 // the explicit Q1 is formed on the second stream while X is factored on
 // this one, and the two meet before Q = Q1 gs(X).
-void qr_projector(ctm_ctx* c, DType e, bool update) {
+const double* qr_projector(ctm_ctx* c, DType e, bool update) {
   hipStream_t s = c->stream;
   const int chi = c->chi;
   const int n = c->chi_c * c->D2;
@@ -227,8 +228,7 @@ void qr_projector(ctm_ctx* c, DType e, bool update) {
   gemm(s, e, n, chi, n, Operand{c->Ct, n, false}, Operand{c->W, n, true},
        Output{c->MP, ldmp, DType::F64}, 1, 1, 1.0, 0.0, c->ws, 0, nullptr,
        big_gemm_events(c, ev, n, chi, n));
-  CTM_HIP(hipMemcpy2DAsync(X, (size_t)ldmp * sizeof(double), Pref, (size_t)chi * sizeof(double),
-                           (size_t)chi * sizeof(double), (size_t)n, hipMemcpyDeviceToDevice, s));
+  launch_copy_block(s, Pref, chi, X, ldmp, n, chi);
   householder_qr(s, c->MP, ldmp, n, chi, c->qr, ldmp);
   // Q1 into M on the second stream
   CTM_HIP(hipEventRecord(c->ev_fork, s));
@@ -238,10 +238,12 @@ void qr_projector(ctm_ctx* c, DType e, bool update) {
   // basis: Q = Q1 gs(X), X = Q1^T P_prev
   gram_schmidt_small(c, X, ldmp, chi, c->Xq);
   CTM_HIP(hipStreamWaitEvent(s, c->ev_join, 0));
+  // P_prev has been read by now (into MP and W), so with update the new
+  // projector goes straight into its place
+  double* Qout = update ? c->P : c->Q;
   gemm(s, DType::F64, n, chi, chi, Operand{c->M, chi, false}, Operand{c->Xq, chi, false},
-       Output{c->Q, chi, DType::F64}, 1, 1, 1.0, 0.0, c->ws);
-  if (update)
-    CTM_HIP(hipMemcpyAsync(c->P, c->Q, (size_t)n * chi * sizeof(double), hipMemcpyDeviceToDevice, s));
+       Output{Qout, chi, DType::F64}, 1, 1, 1.0, 0.0, c->ws);
+  return Qout;
 }
 
 // Projector of the eigendecomposition rule (Fig. 3c) into c->Q: the chi
@@ -260,9 +262,14 @@ void evd_projector(ctm_ctx* c, DType e, bool update) {
   }
 }
 
-void projector(ctm_ctx* c, DType e, bool update) {
-  if (c->cfg.proj == CTM_PROJ_EVD) evd_projector(c, e, update);
-  else qr_projector(c, e, update);
+// Projector for the current Ct; returns where it is (c->Q, or c->P for the
+// QR rule with update).
+const double* projector(ctm_ctx* c, DType e, bool update) {
+  if (c->cfg.proj == CTM_PROJ_EVD) {
+    evd_projector(c, e, update);
+    return c->Q;
+  }
+  return qr_projector(c, e, update);
 }
 
 void step_once(ctm_ctx* c) {
@@ -276,19 +283,20 @@ void step_once(ctm_ctx* c) {
   stage_end(c, CTM_STAGE_CORNER);
   stage_begin(c, CTM_STAGE_PROJECTOR);
   int xn;
+  const double* Qp = c->Q;
   if (n <= chi) {
     xn = (int)n;
     launch_eye(s, c->Q, DType::F64, (int)n, (int)n, n);
   } else {
     xn = chi;
-    projector(c, e, true);
+    Qp = projector(c, e, true);
   }
   stage_end(c, CTM_STAGE_PROJECTOR);
   stage_begin(c, CTM_STAGE_RENORM_C);
   // Q^T in the products' arithmetic (xn x n), contiguous along n for all four
   // products that use it
   void* QT = c->QE;
-  launch_cast_transpose(s, c->Q, QT, e, (int)n, xn);
+  launch_cast_transpose(s, Qp, QT, e, (int)n, xn);
   KernelEvents ev1, ev2;
   // 6. Gm = Ct Q
   gemm(s, e, (int)n, xn, (int)n, Operand{c->Ct, n, false}, Operand{QT, n, true},

@@ -126,6 +126,17 @@ __global__ void init_env_kernel(int D, double* C, double* T) {
   for (int x = i; x < D * D; x += blockDim.x) T[x] = (x / D == x % D) ? 1.0 : 0.0;
 }
 
+// dst[r][c] = src[r][c] for a rows x cols block (row strides lds, ldd).
+__global__ void copy_block_kernel(const double* __restrict__ src, int64_t lds,
+                                  double* __restrict__ dst, int64_t ldd, int rows, int cols) {
+  const int64_t n = (int64_t)rows * cols;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / cols, c = i % cols;
+    dst[r * ldd + c] = src[r * lds + c];
+  }
+}
+
 template <typename T>
 __global__ void cast_kernel(const double* __restrict__ src, T* __restrict__ dst, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
@@ -281,6 +292,14 @@ void launch_double_layer_open(hipStream_t s, const double* A, int d, int D, int 
 
 void launch_init_env(hipStream_t s, int D, double* C, double* T) {
   init_env_kernel<<<1, 256, 0, s>>>(D, C, T);
+  CTM_LAUNCHED();
+}
+
+void launch_copy_block(hipStream_t s, const double* src, int64_t lds, double* dst, int64_t ldd,
+                       int rows, int cols) {
+  const int64_t n = (int64_t)rows * cols;
+  if (n <= 0) return;
+  copy_block_kernel<<<grid_for(n), 256, 0, s>>>(src, lds, dst, ldd, rows, cols);
   CTM_LAUNCHED();
 }
 

@@ -19,6 +19,9 @@ void launch_double_layer_open(hipStream_t s, const double* A, int d, int D, int 
 // C = [[1]], T[0][(u,u')][0] = delta_{u u'}.
 void launch_init_env(hipStream_t s, int D, double* C, double* T);
 // dst[i] = (T)src[i].
+// dst[r][c] = src[r][c] for a rows x cols FP64 block (row strides lds, ldd).
+void launch_copy_block(hipStream_t s, const double* src, int64_t lds, double* dst, int64_t ldd,
+                       int rows, int cols);
 void launch_cast(hipStream_t s, const double* src, void* dst, DType t, int64_t n);
 // dst (cols x rows, leading dimension rows) = (T) transpose of src (rows x
 // cols, leading dimension cols).

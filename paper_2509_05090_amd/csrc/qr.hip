@@ -72,10 +72,12 @@ __device__ __forceinline__ double sum_x16(double v) {
 
 // Register layout of a row block of at most 16 TR rows held by the 256
 // threads: lane l = 16 g + i of wavefront v holds, in a[t][h], row
-// 4 (TR v + t) + g (t < TR) of column i + 16 h (h < NBT / 16).  A column is
-// then spread over the 4 row groups g (and the 4 wavefronts), a row over the
+// 16 t + 4 v + g (t < TR) of column i + 16 h (h < NBT / 16).  A column is
+// then spread over the 4 row groups g and the 4 wavefronts, a row over the
 // 16 lanes i of a row group.  Rows 0 .. NBT-1 (the diagonal block) are in
-// wavefront 0, registers t < NBT / 4.
+// registers t < NBT / 16 of every wavefront, so the per-column work on the
+// diagonal block (masking the pivot column, picking the pivot row) is
+// spread over the wavefronts instead of lengthening one of them.
 template <int NBT>
 constexpr int slots_of() { return NBT / 16; }
 
@@ -99,27 +101,20 @@ template <int NBT, int TR, int H>
 __device__ __forceinline__ void qr_column(double (&a)[TR][NBT / 16], double (&sc)[NBT / 16],
                                           int k, QrShared<NBT>& sh) {
   constexpr int SL = NBT / 16;
-  constexpr int TD = NBT / 4;  // registers holding the diagonal block (wavefront 0)
+  constexpr int TD = NBT / 16;  // registers holding rows of the diagonal block
   const int lane = threadIdx.x & 63;
   const int v = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform
   const int g = lane >> 4, i = lane & 15;
   const int par = k & 1;
   // 1. the pivot column below the diagonal, to the lanes of each row group
-  //    (only wavefront 0 holds rows at or above the pivot)
+  //    (rows at or above the pivot are in registers t < TD)
   if (i == (k & 15)) {
-    if (v == 0) {
 #pragma unroll
-      for (int t = 0; t < TR; t += 2) {
-        double x0 = a[t][H], x1 = a[t + 1][H];
-        if (t < TD) {
-          if (4 * t + g <= k) x0 = 0.0;
-          if (4 * (t + 1) + g <= k) x1 = 0.0;
-        }
-        *(double2*)&sh.xs[v][g][t] = double2{x0, x1};
-      }
-    } else {
-#pragma unroll
-      for (int t = 0; t < TR; t += 2) *(double2*)&sh.xs[v][g][t] = double2{a[t][H], a[t + 1][H]};
+    for (int t = 0; t < TR; t += 2) {
+      double x0 = a[t][H], x1 = a[t + 1][H];
+      if (t < TD && 16 * t + 4 * v + g <= k) x0 = 0.0;
+      if (t + 1 < TD && 16 * (t + 1) + 4 * v + g <= k) x1 = 0.0;
+      *(double2*)&sh.xs[v][g][t] = double2{x0, x1};
     }
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -148,9 +143,10 @@ __device__ __forceinline__ void qr_column(double (&a)[TR][NBT / 16], double (&sc
 #pragma unroll
     for (int h = 0; h < SL; ++h) sh.red[par][v][i + 16 * h] = d[h];
   }
-  // the pivot row (row k: wavefront 0, row group k & 3, register k >> 2)
-  if (v == 0 && g == (k & 3)) {
-    const int tk = k >> 2;
+  // the pivot row (row k: wavefront (k >> 2) & 3, row group k & 3,
+  // register k >> 4)
+  if (v == ((k >> 2) & 3) && g == (k & 3)) {
+    const int tk = k >> 4;
 #pragma unroll
     for (int h = 0; h < SL; ++h) {
       double pv = a[0][h];
@@ -265,7 +261,7 @@ __device__ __forceinline__ void local_qr(double (&a)[TR][NBT / 16], int m, int w
   // reflectors: Y[r][c] = scale_c x_c[r] below the diagonal, 1 on it
 #pragma unroll
   for (int t = 0; t < TR; ++t) {
-    const int r = 4 * (TR * v + t) + g;
+    const int r = 16 * t + 4 * v + g;
 #pragma unroll
     for (int h = 0; h < SL; ++h) {
       const int c = i + 16 * h;
@@ -352,7 +348,7 @@ __device__ __forceinline__ void load_block(double (&a)[TR][NBT / 16], const doub
   const int g = lane >> 4, i = lane & 15;
 #pragma unroll
   for (int t = 0; t < TR; ++t) {
-    const int r = 4 * (TR * v + t) + g;
+    const int r = 16 * t + 4 * v + g;
 #pragma unroll
     for (int h = 0; h < SL; ++h) {
       const int c = i + 16 * h;
