@@ -51,6 +51,7 @@ struct ctm_ctx {
   int* flag = nullptr;
   // Intermediates; allocated with 8-byte elements so that they hold any precision.
   void *aE = nullptr, *CE = nullptr, *TE = nullptr, *PE = nullptr, *QE = nullptr;
+  int aE_type = -1;  // DType held in aE (a cast of a), -1 if none
   void *TCp = nullptr, *V = nullptr, *W = nullptr, *Ct = nullptr, *Gm = nullptr, *V2 = nullptr;
   // energy
   double *XO = nullptr, *EO = nullptr, *Cr2 = nullptr, *Cr4 = nullptr, *Cr5 = nullptr;

@@ -163,7 +163,10 @@ void enlarged_corner(ctm_ctx* c, DType e) {
     CE = c->CE;
     TE = c->TE;
     aE = c->aE;
-    launch_cast(s, c->a, c->aE, e, (int64_t)D2 * D2 * D2);
+    if (c->aE_type != (int)e) {  // a changes only with the site tensor
+      launch_cast(s, c->a, c->aE, e, (int64_t)D2 * D2 * D2);
+      c->aE_type = (int)e;
+    }
   }
   // 1. TCp[beta][gamma][j]
   gemm(s, e, x, D2, x, Operand{CE, x, false}, Operand{TE, x, true, (int64_t)D2 * x},
@@ -592,6 +595,7 @@ int ctm_init(ctm_ctx** out, const ctm_config* cfg, const double* A_dev, const do
       return CTM_ENOTSYM;
     }
     launch_double_layer(s, c->A, c->d, c->D, c->a);
+    c->aE_type = -1;
     launch_init_env(s, c->D, c->C, c->T);
     CTM_HIP(hipMemsetAsync(c->flag, 0, sizeof(int), s));
     CTM_HIP(hipStreamSynchronize(s));
@@ -750,6 +754,7 @@ int ctm_update_tensor(ctm_ctx* c, const double* A_dev) {
     }
     CTM_HIP(hipMemcpyAsync(c->A, A_dev, dA * sizeof(double), hipMemcpyDeviceToDevice, s));
     launch_double_layer(s, c->A, c->d, c->D, c->a);
+    c->aE_type = -1;
     if (c->aO) {
       launch_double_layer_open(s, c->A, c->d, c->D, 0, c->aO);
       launch_double_layer_open(s, c->A, c->d, c->D, 1, c->aOr);

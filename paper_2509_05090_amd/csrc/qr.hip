@@ -215,7 +215,10 @@ __device__ __forceinline__ void qr_column(double (&a)[TR][NBT / 16], double (&sc
     wv[h] = p[h] + scale * f[h];  // v . a_c
     uv[h] = (i + 16 * h > k) ? ts * wv[h] : 0.0;
   }
-  if (v == 0 && g == 0) {
+  // row k of R, column k of the Gram matrix and tau: every wavefront holds
+  // these values; the writer rotates over the wavefronts, two away from the
+  // one that picked the pivot row
+  if (v == (((k >> 2) + 2) & 3) && g == 0) {
 #pragma unroll
     for (int h = 0; h < SL; ++h) {
       const int c = i + 16 * h;
