@@ -2,9 +2,12 @@
 //
 // The corner is small (chi x chi) and the test runs every few steps, on a
 // copy taken after the stream is synchronized.  Eigenvalues of the real
-// symmetric matrix: Householder reduction to tridiagonal form, then
-// bisection on Sturm sequence counts (Golub & Van Loan, Matrix
-// Computations, Secs. 8.3.1 and 8.4.1).
+// symmetric matrix: Householder reduction to tridiagonal form (Golub & Van
+// Loan, Matrix Computations, Sec. 8.3.1; the symmetric updates on the lower
+// triangle only), then the symmetric QR iteration with implicit Wilkinson
+// shifts (Alg. 8.3.2, 8.3.3), O(n^2) for all eigenvalues.  Bisection on
+// Sturm sequence counts (Sec. 8.4.1) remains as the fallback should the
+// iteration not settle.
 #include "spectrum.hpp"
 
 #include <algorithm>
@@ -17,8 +20,9 @@ namespace ctm {
 
 namespace {
 
-// Reduce the symmetric n x n matrix A (row-major, overwritten) to
-// tridiagonal form: diagonal d[0..n), off-diagonal e[0..n-1).
+// Reduce the symmetric n x n matrix A (row-major, overwritten; only the
+// lower triangle is read and updated) to tridiagonal form: diagonal d[0..n),
+// off-diagonal e[0..n-1).
 void tridiagonalize(std::vector<double>& A, int n, std::vector<double>& d,
                     std::vector<double>& e) {
   auto at = [&](int r, int c) -> double& { return A[(size_t)r * n + c]; };
@@ -27,36 +31,97 @@ void tridiagonalize(std::vector<double>& A, int n, std::vector<double>& d,
   e.assign(n > 1 ? n - 1 : 0, 0.0);
   for (int k = 0; k + 2 < n; ++k) {
     const int m = n - k - 1;  // length of the column below the diagonal
+    const int o = k + 1;      // first row / column of the trailing block B
     double xn = 0.0;
-    for (int i = 0; i < m; ++i) xn += at(k + 1 + i, k) * at(k + 1 + i, k);
+    for (int i = 0; i < m; ++i) xn += at(o + i, k) * at(o + i, k);
     xn = std::sqrt(xn);
-    const double x0 = at(k + 1, k);
+    const double x0 = at(o, k);
     if (xn == 0.0) continue;
     const double alpha = x0 > 0.0 ? -xn : xn;
     double vv = 0.0;
     for (int i = 0; i < m; ++i) {
-      v[i] = at(k + 1 + i, k) - (i == 0 ? alpha : 0.0);
+      v[i] = at(o + i, k) - (i == 0 ? alpha : 0.0);
       vv += v[i] * v[i];
     }
     if (vv == 0.0) continue;
-    // p = (2/vv) B v with B the trailing block; w = p - (v^T p / vv) v.
+    // p = (2/vv) B v from the lower triangle of B; w = p - (v^T p / vv) v.
+    for (int i = 0; i < m; ++i) p[i] = 0.0;
     for (int i = 0; i < m; ++i) {
-      double t = 0.0;
-      for (int j = 0; j < m; ++j) t += at(k + 1 + i, k + 1 + j) * v[j];
-      p[i] = 2.0 * t / vv;
+      const double* row = &at(o + i, o);
+      double t = row[i] * v[i];
+      const double vi = v[i];
+      for (int j = 0; j < i; ++j) {
+        t += row[j] * v[j];
+        p[j] += row[j] * vi;
+      }
+      p[i] += t;
     }
+    for (int i = 0; i < m; ++i) p[i] *= 2.0 / vv;
     double vp = 0.0;
     for (int i = 0; i < m; ++i) vp += v[i] * p[i];
     const double K = vp / vv;
     for (int i = 0; i < m; ++i) w[i] = p[i] - K * v[i];
-    for (int i = 0; i < m; ++i)
-      for (int j = 0; j < m; ++j) at(k + 1 + i, k + 1 + j) -= v[i] * w[j] + w[i] * v[j];
-    at(k + 1, k) = alpha;
-    at(k, k + 1) = alpha;
-    for (int i = 1; i < m; ++i) at(k + 1 + i, k) = at(k, k + 1 + i) = 0.0;
+    // B -= v w^T + w v^T on the lower triangle
+    for (int i = 0; i < m; ++i) {
+      double* row = &at(o + i, o);
+      const double vi = v[i], wi = w[i];
+      for (int j = 0; j <= i; ++j) row[j] -= vi * w[j] + wi * v[j];
+    }
+    at(o, k) = alpha;
   }
   for (int i = 0; i < n; ++i) d[i] = at(i, i);
   for (int i = 0; i + 1 < n; ++i) e[i] = at(i + 1, i);
+}
+
+// One implicit symmetric QR step with Wilkinson shift on the unreduced
+// block [p, q] of the tridiagonal (d, e) (Golub & Van Loan, Alg. 8.3.2).
+// The rotation in plane (k, k+1) is G = [c -s; s c] with G^T (x, z) = (r, 0):
+// at k = p, (x, z) is the shifted first column; afterwards x = T(k, k-1) and
+// z the bulge T(k+1, k-1) left by the previous rotation.
+void implicit_qr_step(std::vector<double>& d, std::vector<double>& e, int p, int q) {
+  const double t2 = e[q - 1] * e[q - 1];
+  const double h = 0.5 * (d[q - 1] - d[q]);
+  const double den = h + std::copysign(std::sqrt(h * h + t2), h == 0.0 ? 1.0 : h);
+  const double mu = den == 0.0 ? d[q] : d[q] - t2 / den;
+  double x = d[p] - mu, z = e[p];
+  for (int k = p; k < q; ++k) {
+    const double r = std::hypot(x, z);
+    const double c = r == 0.0 ? 1.0 : x / r, s = r == 0.0 ? 0.0 : z / r;
+    if (k > p) e[k - 1] = r;
+    const double a = d[k], b = e[k], dd = d[k + 1];
+    d[k] = c * c * a + 2.0 * c * s * b + s * s * dd;
+    d[k + 1] = s * s * a - 2.0 * c * s * b + c * c * dd;
+    e[k] = c * s * (dd - a) + (c * c - s * s) * b;
+    if (k + 1 < q) {
+      x = e[k];
+      z = s * e[k + 1];  // new bulge T(k+2, k)
+      e[k + 1] *= c;
+    }
+  }
+}
+
+// Eigenvalues of the tridiagonal (d, e) by the symmetric QR iteration
+// (Golub & Van Loan, Alg. 8.3.3): off-diagonals below eps (|d_i| + |d_i+1|)
+// are set to zero and the trailing unreduced block takes an implicit step
+// until the matrix is diagonal.  False if it has not settled after 30 n
+// steps.
+bool tridiag_qr_eigenvalues(std::vector<double> d, std::vector<double> e,
+                            std::vector<double>& out) {
+  const int n = (int)d.size();
+  int q = n - 1, steps = 0;
+  while (q > 0) {
+    for (int i = 0; i < q; ++i)
+      if (std::fabs(e[i]) <= DBL_EPSILON * (std::fabs(d[i]) + std::fabs(d[i + 1]))) e[i] = 0.0;
+    while (q > 0 && e[q - 1] == 0.0) --q;
+    if (q == 0) break;
+    int p = q - 1;
+    while (p > 0 && e[p - 1] != 0.0) --p;
+    if (++steps > 30 * n) return false;
+    implicit_qr_step(d, e, p, q);
+  }
+  std::sort(d.begin(), d.end());
+  out = std::move(d);
+  return true;
 }
 
 // Number of eigenvalues of the tridiagonal (d, e) below x (Sturm count via
@@ -81,6 +146,8 @@ std::vector<double> symmetric_eigenvalues(std::vector<double> A, int n) {
   if (n == 1) return {A[0]};
   std::vector<double> d, e;
   tridiagonalize(A, n, d, e);
+  std::vector<double> ev;
+  if (tridiag_qr_eigenvalues(d, e, ev)) return ev;
   double lo = d[0], hi = d[0];
   for (int i = 0; i < n; ++i) {
     const double r = (i > 0 ? std::fabs(e[i - 1]) : 0.0) + (i + 1 < n ? std::fabs(e[i]) : 0.0);
@@ -88,7 +155,7 @@ std::vector<double> symmetric_eigenvalues(std::vector<double> A, int n) {
     hi = std::max(hi, d[i] + r);
   }
   const double scale = std::max(std::fabs(lo), std::fabs(hi));
-  std::vector<double> ev(n);
+  ev.assign(n, 0.0);
   for (int j = 0; j < n; ++j) {
     double a = lo, b = hi;
     for (int it = 0; it < 200; ++it) {
