@@ -32,6 +32,10 @@ struct ctm_ctx {
   // the basis matrix is factored on `stream`), joined by ev_fork / ev_join
   hipStream_t stream2 = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // convergence test: pinned host copy of the corner taken before a batch's
+  // last step, and the event marking the copy
+  double* hostC = nullptr;
+  hipEvent_t ev_spec = nullptr;
   std::string err;
   bool poisoned = false;
   int d = 0, D = 0, D2 = 0, chi = 0;
@@ -108,6 +112,8 @@ struct ctm_ctx {
     }
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
+    if (ev_spec) (void)hipEventDestroy(ev_spec);
+    if (hostC) (void)hipHostFree(hostC);
     ctm::free_grad(grad);
     for (hipEvent_t e : event_pool) (void)hipEventDestroy(e);
     for (void* p : allocations) (void)hipFree(p);

@@ -339,12 +339,24 @@ void step_once(ctm_ctx* c) {
 
 int do_steps(ctm_ctx* c, int n_steps, double* delta) {
   if (n_steps < 0) throw std::invalid_argument("n_steps < 0");
+  int pend_x = 0;  // corner dimension of a pending copy taken before the last step
   for (int i = 0; i < n_steps; ++i) {
     if (delta && i == n_steps - 1 && c->spec_step != c->steps) {
-      c->spec = current_spectrum(c);
-      c->spec_step = c->steps;
+      // the corner before the last step goes to pinned host memory without a
+      // stream synchronization; its spectrum is computed while the GPU runs
+      // the last step
+      pend_x = c->chi_c;
+      CTM_HIP(hipMemcpyAsync(c->hostC, c->C, (size_t)pend_x * pend_x * sizeof(double),
+                             hipMemcpyDeviceToHost, c->stream));
+      CTM_HIP(hipEventRecord(c->ev_spec, c->stream));
     }
     step_once(c);
+  }
+  if (pend_x > 0) {
+    CTM_HIP(hipEventSynchronize(c->ev_spec));
+    c->spec = normalized_spectrum(
+        std::vector<double>(c->hostC, c->hostC + (size_t)pend_x * pend_x), pend_x);
+    c->spec_step = c->steps - 1;
   }
   if (delta) {
     if (n_steps == 0 || c->spec_step != c->steps - 1) {
@@ -512,6 +524,8 @@ void allocate(ctm_ctx* c) {
   CTM_HIP(hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking));
   CTM_HIP(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
   CTM_HIP(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+  CTM_HIP(hipEventCreateWithFlags(&c->ev_spec, hipEventDisableTiming));
+  CTM_HIP(hipHostMalloc((void**)&c->hostC, (size_t)chi * chi * sizeof(double), hipHostMallocDefault));
   if (c->cfg.proj == CTM_PROJ_EVD)
     c->evd = evd_work_carve(c->alloc(evd_work_bytes((int)nmax, (int)chi)), (int)nmax, (int)chi);
   size_t wsb = std::max(gemm_scratch_bytes(DType::F64, (int)nmax, (int)chi),
