@@ -406,19 +406,30 @@ constexpr int ACW = 16;   // columns per workgroup
 // handles leaf x, rows [j0 + x rpl, ...) of B, reflectors Y[row][j0 + q]
 // (leading dimension ldy), T = Tsrc + x NBT^2.  Stacked mode: the L*w stacked
 // rows (leaf i, offset t) -> row j0 + i rpl + t, reflectors
-// Ysrc[(i w + t) NBT + q], T = Tsrc.  Each workgroup owns 16 columns:
-//   W = Y^T B (NBT x 16): the wavefronts split the rows, partial tiles are
-//       summed in LDS in a fixed order;
+// Ysrc[(i w + t) NBT + q], T = Tsrc.  Each workgroup owns 16 columns and at
+// most 64 RB rows; lane (g, i) of wavefront v holds B at rows
+// 4 v + 64 s + g (s < RB), column i, loaded once:
+//   W = Y^T B (NBT x 16): MFMAs over the lane's rows, partial tiles summed
+//       in LDS in a fixed order;
 //   W <- op(T) W;
-//   B <- B - Y W: 16-row tiles distributed over the wavefronts.
+//   B <- B - Y W: 16-row tiles made of the lane's own rows s = 4 l .. 4 l + 3
+//       (output register e of lane (g, i) is row 4 v + 64 (4 l + e) + g), so
+//       B is updated from the registers it was loaded into; the Y operands
+//       of this phase are loaded before the reduction of W.
+template <int NBT>
+constexpr int apply_row_steps() { return NBT == 32 ? 8 : 16; }
+
 template <int NBT, bool STACKED, bool TRANS>
 __global__ __launch_bounds__(AT) void qr_apply_kernel(double* __restrict__ B, int ldb, int c0, int c1,
                                                       const double* __restrict__ Ysrc, int ldy,
                                                       const double* __restrict__ Tsrc, int n, int j0,
                                                       int w, int rpl, int L) {
   constexpr int NT = NBT / 16;
+  constexpr int RB = apply_row_steps<NBT>();
+  constexpr int TL = RB / 4;  // 16-row tiles per lane set
   __shared__ double Wp[AW][NBT][ACW + 1];
   __shared__ double W[NBT][ACW + 1];
+  __shared__ double W2[NBT][ACW + 1];
   __shared__ double Tsh[NBT][NBT + 1];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int i16 = lane & 15, grp = lane >> 4;
@@ -448,30 +459,36 @@ __global__ __launch_bounds__(AT) void qr_apply_kernel(double* __restrict__ B, in
     return (r < rows && q < w) ? Yb[(int64_t)r * ys + q] : 0.0;
   };
   auto bat = [&](int r) -> double { return (r < rows && colok) ? B[grow(r) * ldb + col] : 0.0; };
+  auto lrow = [&](int st) -> int { return 4 * wv + 64 * st + grp; };
+
+  double bb[RB], yb[RB][NT];
+#pragma unroll
+  for (int st = 0; st < RB; ++st) {
+    bb[st] = bat(lrow(st));
+#pragma unroll
+    for (int t = 0; t < NT; ++t) yb[st][t] = yat(lrow(st), 16 * t + i16);
+  }
   for (int i = tid; i < NBT * NBT; i += AT) Tsh[i / NBT][i % NBT] = T[i];
 
-  // W = Y^T B: wavefront wv takes the 4-row steps k0 = 4 (wv + AW s); the
-  // loads of a batch of steps are issued before its products.
+  // W = Y^T B over the lane's rows; result register e of lane (grp, i16)
+  // holds W[16 t + 4 e + grp][i16]
   d4v acc[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = d4v{0.0, 0.0, 0.0, 0.0};
-  constexpr int KB = 8;  // steps per batch
-  for (int k0 = 4 * wv; k0 < rows; k0 += 4 * AW * KB) {
-    double yb[KB][NT], bb[KB];
 #pragma unroll
-    for (int it = 0; it < KB; ++it) {
-      const int r = k0 + 4 * AW * it + grp;
-      bb[it] = bat(r);
+  for (int st = 0; st < RB; ++st)
 #pragma unroll
-      for (int t = 0; t < NT; ++t) yb[it][t] = yat(r, 16 * t + i16);
-    }
+    for (int t = 0; t < NT; ++t)
+      acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(yb[st][t], bb[st], acc[t], 0, 0, 0);
+  // Y operands of the update: tile l, row index i16 -> lane row set
+  // 4 wv + 64 (4 l + (i16 >> 2)) + (i16 & 3), reflector 4 s + grp
+  double ya[TL][NBT / 4];
 #pragma unroll
-    for (int it = 0; it < KB; ++it)
+  for (int l = 0; l < TL; ++l) {
+    const int rr = 4 * wv + 64 * (4 * l + (i16 >> 2)) + (i16 & 3);
 #pragma unroll
-      for (int t = 0; t < NT; ++t)
-        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(yb[it][t], bb[it], acc[t], 0, 0, 0);
+    for (int s = 0; s < NBT / 4; ++s) ya[l][s] = yat(rr, 4 * s + grp);
   }
-  // result layout: register e of lane (grp, i16) holds row 4 e + grp, column i16
 #pragma unroll
   for (int t = 0; t < NT; ++t)
 #pragma unroll
@@ -485,34 +502,29 @@ __global__ __launch_bounds__(AT) void qr_apply_kernel(double* __restrict__ B, in
     W[q][j] = s;
   }
   __syncthreads();
-  // W <- op(T) W (T upper triangular, zeros below the diagonal)
-  double w2 = 0.0;
+  // W2 = op(T) W (T upper triangular, zeros below the diagonal)
   if (tid < NBT * ACW) {
     const int q = tid / ACW, j = tid % ACW;
+    double w2 = 0.0;
 #pragma unroll
     for (int p = 0; p < NBT; ++p) w2 += (TRANS ? Tsh[p][q] : Tsh[q][p]) * W[p][j];
+    W2[q][j] = w2;
   }
   __syncthreads();
-  if (tid < NBT * ACW) W[tid / ACW][tid % ACW] = w2;
-  __syncthreads();
-  // B <- B - Y W on 16-row tiles: A operand Y[r0 + i16][k], B operand W[k][i16]
+  // B <- B - Y W2 on the lane's rows
   double wop[NBT / 4];
 #pragma unroll
-  for (int s = 0; s < NBT / 4; ++s) wop[s] = W[4 * s + grp][i16];
-  for (int r0 = 16 * wv; r0 < rows; r0 += 16 * AW) {
-    double ya[NBT / 4], bo[4];
+  for (int s = 0; s < NBT / 4; ++s) wop[s] = W2[4 * s + grp][i16];
 #pragma unroll
-    for (int s = 0; s < NBT / 4; ++s) ya[s] = yat(r0 + i16, 4 * s + grp);
-#pragma unroll
-    for (int e = 0; e < 4; ++e) bo[e] = bat(r0 + 4 * e + grp);
+  for (int l = 0; l < TL; ++l) {
     d4v acc3 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int s = 0; s < NBT / 4; ++s)
-      acc3 = __builtin_amdgcn_mfma_f64_16x16x4f64(ya[s], wop[s], acc3, 0, 0, 0);
+      acc3 = __builtin_amdgcn_mfma_f64_16x16x4f64(ya[l][s], wop[s], acc3, 0, 0, 0);
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const int r = r0 + 4 * e + grp;
-      if (r < rows && colok) B[grow(r) * ldb + col] = bo[e] - acc3[e];
+      const int r = lrow(4 * l + e);
+      if (r < rows && colok) B[grow(r) * ldb + col] = bb[4 * l + e] - acc3[e];
     }
   }
 }
@@ -591,6 +603,9 @@ void launch_apply_nb(hipStream_t s, bool stacked, bool trans, const QrPanel& p, 
 void launch_apply(hipStream_t s, bool stacked, bool trans, const QrPanel& p, double* B, int ldb,
                   int c0, int c1, int n, const QrWork& w, int panel) {
   if (c1 <= c0) return;
+  const int maxrows = 64 * (p.nb == 32 ? apply_row_steps<32>() : apply_row_steps<16>());
+  if ((stacked ? p.L * p.w : p.rpl) > maxrows)
+    throw std::logic_error("qr apply: more rows per workgroup than the kernel holds");
   if (p.nb == 32) launch_apply_nb<32>(s, stacked, trans, p, B, ldb, c0, c1, n, w, panel);
   else launch_apply_nb<16>(s, stacked, trans, p, B, ldb, c0, c1, n, w, panel);
 }
