@@ -156,13 +156,16 @@ def test_gemm_small_batches(prec, nb0, nb1, M, N, K, ta, tb):
 
 
 QR_SHAPES = [(16, 16), (40, 16), (200, 37), (1024, 64), (1600, 100), (5184, 144), (144, 144),
-             (513, 33), (1025, 64), (9000, 100), (16384, 256), (30000, 40), (7, 1)]
+             (513, 33), (1025, 64), (9000, 100), (16384, 256), (30000, 40), (7, 1),
+             (512, 40), (8192, 64)]
 
 
 @pytest.mark.parametrize("n,k", QR_SHAPES)
 def test_householder_qr(n, k):
     """Shapes with one leaf, several leaves (ragged last leaf), two rows per
-    thread in the leaves (n > 8192) and in the stacked factorization."""
+    thread in the leaves (n > 8192) and in the stacked factorization; leaves
+    and stacked rows at the 512 (32-column panels) and 1024 (16-column)
+    rows a workgroup holds (512 x 40, 8192 x 64, 16384 x 256)."""
     M = _rng(n + k).standard_normal((n, k))
     Q, R = ctm.qr(torch.tensor(M, device=DEV))
     torch.cuda.synchronize()
