@@ -522,8 +522,10 @@ void allocate(ctm_ctx* c) {
   c->qr2 = qr_work_carve(c->stream, c->alloc(qr_work_bytes((int)chi, (int)chi)), (int)chi,
                          (int)chi);
   CTM_HIP(hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking));
-  CTM_HIP(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
-  CTM_HIP(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+  // fork/join of the projector's two streams: an ordering within the device,
+  // so no system-scope fence (host and other devices never read through them)
+  CTM_HIP(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming | hipEventDisableSystemFence));
+  CTM_HIP(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming | hipEventDisableSystemFence));
   CTM_HIP(hipEventCreateWithFlags(&c->ev_spec, hipEventDisableTiming));
   CTM_HIP(hipHostMalloc((void**)&c->hostC, (size_t)chi * chi * sizeof(double), hipHostMallocDefault));
   if (c->cfg.proj == CTM_PROJ_EVD)
