@@ -14,6 +14,8 @@
 // is scattered into the k-contiguous LDS rows.
 #include "gemm.hpp"
 
+#include <algorithm>
+
 namespace ctm {
 
 typedef double d4v __attribute__((ext_vector_type(4)));
@@ -560,7 +562,152 @@ __global__ __launch_bounds__(256) void small_batch_kernel(SmallBatchArgs g) {
   }
 }
 
+// The same batches when A is stored with its rows contiguous
+// (A[b0](row, k) = A[b0 sA0 + k lda + row]) and the output rows take whole
+// 16-byte groups of columns (FP64, FP32).  A workgroup holds in LDS the
+// 16-row slices of AG consecutive batches b0 ([b0][k][row], filled with
+// 16-byte loads); each of its four wavefronts keeps one B[b1] in registers
+// and sweeps those AG batches, reading the next batch's fragments from LDS
+// while the products of the current one run.  The MFMA computes the
+// transposed 16 x 16 tile (rows = output columns, columns = output rows),
+// so a lane ends with four adjacent columns of one output row and writes
+// them with one vector store; the FP64 result interleaves rows across the
+// lane groups, which the row order of the B fragment undoes.  For the V3
+// product the outputs of consecutive b0 are adjacent in a row, so a
+// wavefront writes whole row segments of AG*N elements.
+struct SmallBatchRowsArgs {
+  int M, N, K;
+  const void* A;
+  int64_t lda, sA0;
+  const void* B;
+  int64_t ldb, sB1;
+  bool bt;
+  void* C;
+  int64_t ldc, sC0, sC1;
+  int nb0, nb1;
+  int ag;      // batches b0 per workgroup
+  int mtiles;  // 16-row tiles
+};
+
+template <typename E, int KS, int NT>
+__global__ __launch_bounds__(256) void small_batch_rows_kernel(SmallBatchRowsArgs g) {
+  using MF = Mfma<E>;
+  using accv = typename MF::accv;
+  typedef E v4 __attribute__((ext_vector_type(4)));
+  constexpr int KPAD = KS * 4;
+  extern __shared__ __attribute__((aligned(16))) unsigned char sbr_lds[];
+  v4* As4 = (v4*)sbr_lds;  // [ag][KPAD][16] elements
+  const E* As = (const E*)sbr_lds;
+
+  const int r0 = (blockIdx.x % g.mtiles) * 16, a0 = (blockIdx.x / g.mtiles) * g.ag;
+  const int na = min(g.ag, g.nb0 - a0);
+  {
+    // row (a, k) of the tile = 16 elements = 4 vectors; M is a multiple of 4
+    constexpr int LB = 8;
+    const E* __restrict__ A = (const E*)g.A;
+    const int tot4 = g.ag * KPAD * 4;
+    for (int base = 0; base < tot4; base += 256 * LB) {
+      v4 v[LB];
+#pragma unroll
+      for (int j = 0; j < LB; ++j) {
+        const int i4 = base + threadIdx.x + 256 * j, row = i4 >> 2, q = i4 & 3;
+        const int k = row % KPAD, a = row / KPAD;
+        v[j] = v4{0, 0, 0, 0};
+        if (i4 < tot4 && a < na && k < g.K && r0 + 4 * q < g.M)
+          v[j] = *(const v4*)(A + (int64_t)(a0 + a) * g.sA0 + (int64_t)k * g.lda + r0 + 4 * q);
+      }
+#pragma unroll
+      for (int j = 0; j < LB; ++j) {
+        const int i4 = base + threadIdx.x + 256 * j;
+        if (i4 < tot4) As4[i4] = v[j];
+      }
+    }
+  }
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int r16 = lane & 15, grp = lane >> 4;
+  const int b1 = blockIdx.y * 4 + wid;
+  if (b1 >= g.nb1) return;
+  // fragment row r16 of column tile t holds output column t*16 + prow
+  const int prow = MF::ROWS_INTERLEAVED ? 4 * (r16 & 3) + (r16 >> 2) : r16;
+  E bf[NT][KS];
+  {
+    const E* __restrict__ B = (const E*)g.B + (int64_t)b1 * g.sB1;
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        const int n = t * 16 + prow, k = s * 4 + grp;
+        bf[t][s] = zero_of<E>();
+        if (n < g.N && k < g.K) bf[t][s] = g.bt ? B[(int64_t)n * g.ldb + k] : B[(int64_t)k * g.ldb + n];
+      }
+  }
+  const bool rowok = r0 + r16 < g.M;
+  E* __restrict__ Cl =
+      (E*)g.C + (int64_t)b1 * g.sC1 + (int64_t)(r0 + r16) * g.ldc + 4 * grp;
+  E af[KS], an[KS];
+#pragma unroll
+  for (int s = 0; s < KS; ++s) af[s] = As[(s * 4 + grp) * 16 + r16];
+  for (int a = 0; a < na; ++a) {
+    const int a1 = a + 1 < na ? a + 1 : a;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) an[s] = As[(a1 * KPAD + s * 4 + grp) * 16 + r16];
+    accv acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = accv{0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[t] = MF::mma(&bf[t][s], &af[s], acc[t]);
+    E* __restrict__ Ca = Cl + (int64_t)(a0 + a) * g.sC0;
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+      if (rowok && t * 16 + 4 * grp < g.N)
+        *(v4*)(Ca + t * 16) = v4{acc[t][0], acc[t][1], acc[t][2], acc[t][3]};
+#pragma unroll
+    for (int s = 0; s < KS; ++s) af[s] = an[s];
+  }
+}
+
 namespace {
+
+// Launches the row-layout small-batch kernel if the operands allow it.
+bool small_batch_rows(hipStream_t s, DType e, int M, int N, int K, const Operand& A,
+                      const Operand& B, const Output& C, int nb0, int nb1, int ks, int nt) {
+  const int es = (int)dtype_size(e);
+  auto al = [&](const void* p) { return ((uintptr_t)p % (4 * (uintptr_t)es)) == 0; };
+  if (e == DType::BF16 || !A.trans || M % 4 || N % 4 || A.ld % 4 || A.s0 % 4 || C.ld % 4 ||
+      C.s0 % 4 || C.s1 % 4 || !al(A.p) || !al(C.p))
+    return false;
+  const int kpad = ks * 4;
+  const int64_t per_batch = (int64_t)kpad * 16 * es;  // LDS bytes per batch b0
+  SmallBatchRowsArgs g{};
+  g.ag = (int)std::min<int64_t>({e == DType::F32 ? 16 : 8, SB_LDS / per_batch, nb0});
+  g.mtiles = (int)cdiv(M, 16);
+  g.M = M; g.N = N; g.K = K;
+  g.A = A.p; g.lda = A.ld; g.sA0 = A.s0;
+  g.B = B.p; g.ldb = B.ld; g.sB1 = B.s1; g.bt = B.trans;
+  g.C = C.p; g.ldc = C.ld; g.sC0 = C.s0; g.sC1 = C.s1;
+  g.nb0 = nb0; g.nb1 = nb1;
+  const dim3 grid((unsigned)(g.mtiles * cdiv(nb0, g.ag)), (unsigned)cdiv(nb1, 4));
+  const size_t lds = (size_t)g.ag * per_batch;
+#define CTM_SBR(T, KS_, NT_) small_batch_rows_kernel<T, KS_, NT_><<<grid, 256, lds, s>>>(g)
+  if (e == DType::F32) {
+    if (ks == 1) CTM_SBR(float, 1, 1);
+    else if (ks == 4) CTM_SBR(float, 4, 1);
+    else if (ks == 9) CTM_SBR(float, 9, 3);
+    else CTM_SBR(float, 16, 4);
+  } else {
+    if (ks == 1) CTM_SBR(double, 1, 1);
+    else if (ks == 4) CTM_SBR(double, 4, 1);
+    else if (ks == 9) CTM_SBR(double, 9, 3);
+    else CTM_SBR(double, 16, 4);
+  }
+#undef CTM_SBR
+  CTM_LAUNCHED();
+  return true;
+}
 
 // Launches the small-batch kernel if the product has its shape; false if
 // not (the caller then uses the general kernel).
@@ -589,6 +736,7 @@ bool small_batch(hipStream_t s, DType e, int M, int N, int K, const Operand& A, 
     ks = 16;
     nt = 4;
   }
+  if (small_batch_rows(s, e, M, N, K, A, B, C, nb0, nb1, ks, nt)) return true;
   const int kpad = ks * kstep;
   const int kp = kpad + 16 / es;  // 16 bytes of row padding
   const int64_t mt_fit = SB_LDS / ((int64_t)kp * es) / 16 * 16;

@@ -155,6 +155,62 @@ def test_gemm_small_batches(prec, nb0, nb1, M, N, K, ta, tb):
     assert np.all(out[..., N:] == 7.0)  # padding columns untouched
 
 
+@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("nb0,nb1,M,N,K,tb,ldc", [(5, 7, 144, 36, 36, False, 40),
+                                                   (17, 9, 36, 36, 36, True, 36),
+                                                   (3, 4, 20, 16, 16, False, 20),
+                                                   (2, 5, 64, 64, 64, True, 64),
+                                                   (4, 3, 8, 4, 4, False, 8),
+                                                   (3, 2, 52, 20, 50, True, 24)])
+def test_gemm_small_batches_row_layout(prec, nb0, nb1, M, N, K, tb, ldc):
+    """Small batches with A stored rows-contiguous and output rows of whole
+    4-element groups (the layout of the enlarged-corner pair contractions):
+    every (K, N) instance size, 16-row tiles with a ragged last tile, a last
+    group of b0 batches and of b1 batches only partly filled, both layouts
+    of B; the padding columns of C stay untouched."""
+    r = _rng(nb0 * 2003 + nb1 * 31 + M + N + K + prec + tb)
+    A = r.standard_normal((nb0, K, M))
+    B = r.standard_normal((nb1,) + ((N, K) if tb else (K, N)))
+    Ad = torch.tensor(A, device=DEV).to(TDT[prec])
+    Bd = torch.tensor(B, device=DEV).to(TDT[prec])
+    Cd = torch.full((nb0, nb1, M, ldc), 7.0, device=DEV, dtype=TDT[prec])
+    ctm.gemm(Ad, Bd, Cd, M, N, K, lda=M, ldb=K if tb else N, ldc=ldc, transA=True, transB=tb,
+             prec=prec, batch=(nb0, nb1), sA=(K * M, 0), sB=(0, K * N),
+             sC=(nb1 * M * ldc, M * ldc))
+    torch.cuda.synchronize()
+    Ah, Bh = _stored(A, prec), _stored(B, prec)
+    opB = np.swapaxes(Bh, 1, 2) if tb else Bh
+    ref = np.einsum("akm,bkn->abmn", Ah, opB)
+    scale = np.einsum("akm,bkn->abmn", np.abs(Ah), np.abs(opB)) + 1e-300
+    out = Cd.double().cpu().numpy()
+    err = (np.abs(out[..., :N] - ref) / scale).max()
+    assert err < max(TOL[prec], TOL_OUT[prec]), err
+    assert np.all(out[..., N:] == 7.0)
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("nb0,M", [(20, 44), (9, 144)])
+def test_gemm_small_batches_v3_layout(prec, nb0, M):
+    """The V3 product's output layout: C[(b1, row)][(b0, col)], so the
+    results of consecutive b0 batches sit side by side in one output row
+    (N = K = 36, B read transposed)."""
+    nb1, N, K = 36, 36, 36
+    r = _rng(nb0 * 7 + M + prec)
+    A = r.standard_normal((nb0, K, M))
+    B = r.standard_normal((N, nb1, K))  # B[b1](k, n) = a[n][b1][k]
+    Ad = torch.tensor(A, device=DEV).to(TDT[prec])
+    Bd = torch.tensor(B, device=DEV).to(TDT[prec])
+    Cd = torch.zeros((nb1, M, nb0, N), device=DEV, dtype=TDT[prec])
+    ctm.gemm(Ad, Bd, Cd, M, N, K, lda=M, ldb=nb1 * K, ldc=nb0 * N, transA=True, transB=True,
+             prec=prec, batch=(nb0, nb1), sA=(K * M, 0), sB=(0, K), sC=(N, M * nb0 * N))
+    torch.cuda.synchronize()
+    Ah, Bh = _stored(A, prec), _stored(B, prec)
+    ref = np.einsum("akm,nbk->bman", Ah, Bh)
+    scale = np.einsum("akm,nbk->bman", np.abs(Ah), np.abs(Bh)) + 1e-300
+    err = (np.abs(Cd.double().cpu().numpy() - ref) / scale).max()
+    assert err < max(TOL[prec], TOL_OUT[prec]), err
+
+
 QR_SHAPES = [(16, 16), (40, 16), (200, 37), (1024, 64), (1600, 100), (5184, 144), (144, 144),
              (513, 33), (1025, 64), (9000, 100), (16384, 256), (30000, 40), (7, 1),
              (512, 40), (8192, 64)]
