@@ -52,11 +52,11 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def gpu_rate(ctm, torch, A, G, chi, prec, warmup, steps, n_check=10):
+def gpu_rate(ctm, torch, A, G, chi, prec, warmup, steps, n_check=10, proj="qr"):
     """Steps/s of `steps` timed steps after `warmup` untimed ones (from the
     truncated regime), also with the corner-spectrum check every n_check
     steps, and the stage profile of 10 further steps."""
-    with ctm.Context(A, G, chi, prec=prec) as c:
+    with ctm.Context(A, G, chi, proj=proj, prec=prec) as c:
         c.step(max(warmup, 3))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -78,7 +78,7 @@ def gpu_rate(ctm, torch, A, G, chi, prec, warmup, steps, n_check=10):
     return steps / dt, steps / dt_check, stages, flops
 
 
-def gpu_converged(ctm, torch, A, G, chi, prec, tol, max_steps, h, residuals=None):
+def gpu_converged(ctm, torch, A, G, chi, prec, tol, max_steps, h, residuals=None, proj="qr"):
     """Converge (spectrum check every 10 steps); energy, spectrum, steps, time.
     If `residuals` is a dict it receives the isometry residual max|P^T P - I|
     of the final projector, the fixed-point residual (the largest change of T
@@ -88,7 +88,7 @@ def gpu_converged(ctm, torch, A, G, chi, prec, tol, max_steps, h, residuals=None
     workloads: its spectrum comes in +-lambda pairs and C keeps turning
     within their two-dimensional eigenspaces (the oracle does the same),
     while its spectrum, T, P and the energy converge."""
-    with ctm.Context(A, G, chi, prec=prec) as c:
+    with ctm.Context(A, G, chi, proj=proj, prec=prec) as c:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         steps, delta, ok = c.converge(tol, max_steps, n_check=10)
@@ -292,6 +292,8 @@ def main():
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--modes", default="fp32,fp64,bf16")
+    ap.add_argument("--proj", default="qr", choices=("qr", "qr_chol"),
+                    help="QR projector: Q1 by Householder (qr) or by Cholesky QR (qr_chol)")
     ap.add_argument("--no-large", action="store_true", help="skip the D=8, chi=256 leg")
     ap.add_argument("--no-projectors", action="store_true",
                     help="skip the QR vs eigendecomposition leg (D=5, chi=120)")
@@ -330,7 +332,7 @@ def main():
     for prec in modes:
         log(f"[bench] {prec}: warmup {args.warmup}, timing {args.steps} steps")
         rate, rate_check, stages, flops = gpu_rate(ctm, torch, A, G, w.chi, prec, args.warmup,
-                                                   args.steps)
+                                                   args.steps, proj=args.proj)
         r = {"iters_per_s": rate, "iters_per_s_with_check10": rate_check,
              "stage_ms_per_step": {k: v[0] / 10 for k, v in stages.items()}}
         big_ms, big_n = stages["big_gemm"]
@@ -341,7 +343,7 @@ def main():
             tol = {"fp64": w.tol, "fp32": 1e-8, "bf16": 1e-4}[prec]
             resid = {}
             e, s, steps, delta, ok, dt = gpu_converged(ctm, torch, A, G, w.chi, prec, tol, 4000, h,
-                                                       resid)
+                                                       resid, proj=args.proj)
             r.update({"e_site": e, "converge_tol": tol, "converge_steps": steps,
                       "converge_delta": delta, "converged": ok, "converge_s": dt,
                       "isometry_residual": resid["isometry"],
@@ -359,7 +361,8 @@ def main():
     ladder = None
     if not args.no_converge:
         log("[bench] ladder: BF16 -> FP32 -> FP64, converged to the FP64 tolerance")
-        e, sl, steps, delta, ok, dt = gpu_converged(ctm, torch, A, G, w.chi, "ladder", w.tol, 6000, h)
+        e, sl, steps, delta, ok, dt = gpu_converged(ctm, torch, A, G, w.chi, "ladder", w.tol, 6000, h,
+                                                    proj=args.proj)
         ladder = {"converge_tol": w.tol, "converge_steps": steps, "converge_delta": delta,
                   "converged": ok, "converge_s": dt, "e_site": e}
         if gold_ok:
@@ -429,7 +432,8 @@ def main():
                                "rotated Heisenberg",
                    "d": w.d, "D": w.D, "chi": w.chi, "n": w.n,
                    "precision": "contractions FP32 matrix cores (FP32 accumulate); "
-                                "QR, basis, normalization, energy FP64"},
+                                "QR, basis, normalization, energy FP64",
+                   "qr": "Cholesky QR (3 passes)" if args.proj == "qr_chol" else "Householder"},
         "modes": res,
         "speedup_mixed_vs_fp64": (res["fp32"]["iters_per_s"] / res["fp64"]["iters_per_s"])
         if "fp32" in res and "fp64" in res else None,

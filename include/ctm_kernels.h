@@ -40,6 +40,20 @@ int ctm_gemm(int prec, int M, int N, int K,
  * convention R[j][j] = -sign(pivot) * ||column||.  M_dev is not modified. */
 int ctm_qr(const double *M_dev, int n, int k, double *Q_dev, double *R_dev, void *stream);
 
+/* Cholesky factorization G = R^T R of the symmetric k x k FP64 matrix G_dev
+ * (row-major, lower triangle read; 1 <= k <= 192), taken as the Gram matrix
+ * of an m x k matrix: the factor of the Cholesky QR projector
+ * (CTM_PROJ_QR_CHOL), by one workgroup.  R_dev (k x k) receives the upper
+ * triangle with a positive diagonal, zeros below; Rinv_dev (k x k, nullable)
+ * receives R^{-1}, likewise upper triangular.  If a pivot is not
+ * positive (or below 64 u times its diagonal entry) the factorization is
+ * redone on G + s I, s = 11 (m k + k (k + 1)) u trace(G) (shifted Cholesky
+ * QR, Fukaya et al., SIAM J. Sci. Comput. 42 (2020)), and bit 0 of
+ * *status_host is set; bit 1 if the shifted matrix broke down too (pivots
+ * clamped).  Synchronizes. */
+int ctm_cholesky(const double *G_dev, int k, int m, double *R_dev, double *Rinv_dev,
+                 int *status_host, void *stream);
+
 /* Eigenvectors of the k eigenvalues of largest magnitude of the symmetric
  * n x n FP64 matrix A_dev (row-major, 1 <= k <= n <= 8192; the
  * eigendecomposition projector's solver, Sec. II.B, Fig. 3c).  U_dev (n x k)

@@ -41,6 +41,8 @@
 #include <vector>
 
 #include "ctm.h"
+#include "adjoint_kernels.hpp"
+#include "chol.hpp"
 #include "gemm.hpp"
 #include "kernels.hpp"
 #include "qr.hpp"
@@ -249,6 +251,59 @@ const double* qr_projector(ctm_ctx* c, DType e, bool update) {
   return Qout;
 }
 
+// One Cholesky QR pass: Out = In R^{-1} with R^T R = In^T In (n x chi, ld
+// chi, FP64); the factorization shifts a numerically singular Gram matrix.
+void chol_pass(ctm_ctx* c, const double* In, double* Out, int n, int chi) {
+  hipStream_t s = c->stream;
+  gemm(s, DType::F64, chi, chi, n, Operand{In, chi, true}, Operand{In, chi, false},
+       Output{c->cg, chi, DType::F64}, 1, 1, 1.0, 0.0, c->ws);
+  launch_cholesky(s, c->cg, chi, chi, n, c->cr, chi, c->chol_status, c->flag);
+  launch_tri_inv_upper(s, c->cr, chi, chi, nullptr, c->cri);
+  gemm(s, DType::F64, n, chi, chi, Operand{In, chi, false}, Operand{c->cri, chi, false},
+       Output{Out, chi, DType::F64}, 1, 1, 1.0, 0.0, c->ws);
+}
+
+// The QR projector with Q1 from Cholesky QR instead of Householder: three
+// passes (the first shifted if M^T M is numerically singular) give an
+// orthonormal basis of span(M) to working precision for cond(M) below about
+// 1/u.  The isometry Q = Q1 gs(Q1^T P_prev) depends on Q1 only through
+// span(Q1) = span(M), so it is the same as with the Householder Q1 up to
+// rounding.
+const double* chol_projector(ctm_ctx* c, DType e, bool update) {
+  hipStream_t s = c->stream;
+  const int chi = c->chi;
+  const int n = c->chi_c * c->D2;
+  double* Pref = c->P;
+  if (c->p_rows != n) {
+    if (update) {
+      start_projector(c, n, c->P);
+      c->p_rows = n;
+    } else {
+      Pref = (double*)c->PE;
+      start_projector(c, n, Pref);
+    }
+  }
+  launch_cast_transpose(s, Pref, c->W, e, n, chi);
+  // 5. M = Ct P_prev (FP64 result), then Q1 by three Cholesky QR passes
+  double* M0 = c->MP;
+  double* M1 = c->MP + (int64_t)n * chi;
+  KernelEvents ev;
+  gemm(s, e, n, chi, n, Operand{c->Ct, n, false}, Operand{c->W, n, true},
+       Output{M0, chi, DType::F64}, 1, 1, 1.0, 0.0, c->ws, 0, nullptr,
+       big_gemm_events(c, ev, n, chi, n));
+  chol_pass(c, M0, M1, n, chi);
+  chol_pass(c, M1, M0, n, chi);
+  chol_pass(c, M0, c->M, n, chi);
+  // basis: Q = Q1 gs(X), X = Q1^T P_prev
+  gemm(s, DType::F64, chi, chi, n, Operand{c->M, chi, true}, Operand{Pref, chi, false},
+       Output{c->cx, chi, DType::F64}, 1, 1, 1.0, 0.0, c->ws);
+  gram_schmidt_small(c, c->cx, chi, chi, c->Xq);
+  double* Qout = update ? c->P : c->Q;
+  gemm(s, DType::F64, n, chi, chi, Operand{c->M, chi, false}, Operand{c->Xq, chi, false},
+       Output{Qout, chi, DType::F64}, 1, 1, 1.0, 0.0, c->ws);
+  return Qout;
+}
+
 // Projector of the eigendecomposition rule (Fig. 3c) into c->Q: the chi
 // eigenvectors of Ct of largest |eigenvalue|, column signs following P_prev
 // when it matches n (else largest entry positive).  If update, P_prev <- Q.
@@ -272,6 +327,7 @@ const double* projector(ctm_ctx* c, DType e, bool update) {
     evd_projector(c, e, update);
     return c->Q;
   }
+  if (c->cfg.proj == CTM_PROJ_QR_CHOL) return chol_projector(c, e, update);
   return qr_projector(c, e, update);
 }
 
@@ -476,7 +532,10 @@ bool valid_cfg(const ctm_config* cfg, std::string& why) {
   if (cfg->d < 1 || cfg->D < 1 || cfg->chi < 1) return why = "d, D and chi must be >= 1", false;
   if ((int64_t)cfg->d * cfg->D * cfg->D * cfg->D > 16384) return why = "d*D^3 > 16384", false;
   if ((int64_t)cfg->chi * cfg->D * cfg->D > QR_MAX_ROWS) return why = "chi*D^2 > 32768", false;
-  if (cfg->proj != CTM_PROJ_QR && cfg->proj != CTM_PROJ_EVD) return why = "bad projector", false;
+  if (cfg->proj != CTM_PROJ_QR && cfg->proj != CTM_PROJ_EVD && cfg->proj != CTM_PROJ_QR_CHOL)
+    return why = "bad projector", false;
+  if (cfg->proj == CTM_PROJ_QR_CHOL && cfg->chi > CHOL_KMAX)
+    return why = "the Cholesky QR projector needs chi <= " + std::to_string(CHOL_KMAX), false;
   if (cfg->proj == CTM_PROJ_EVD && (int64_t)cfg->chi * cfg->D * cfg->D > 8192)
     return why = "the eigendecomposition projector needs chi*D^2 <= 8192", false;
   if (cfg->prec < CTM_PREC_FP64 || cfg->prec > CTM_PREC_LADDER) return why = "bad precision", false;
@@ -501,6 +560,13 @@ void allocate(ctm_ctx* c) {
   c->Cp = c->allocd(chi * chi);
   c->Xs = c->allocd(chi * chi);
   c->Xq = c->allocd(chi * chi);
+  if (c->cfg.proj == CTM_PROJ_QR_CHOL) {
+    c->cg = c->allocd(chi * chi);
+    c->cr = c->allocd(chi * chi);
+    c->cri = c->allocd(chi * chi);
+    c->cx = c->allocd(chi * chi);
+    c->chol_status = (int*)c->alloc(sizeof(int) * 4);
+  }
   c->Tp = c->allocd(chi * D2 * chi);
   c->sgn = c->allocd(chi);
   c->sumsq = c->allocd(1024);

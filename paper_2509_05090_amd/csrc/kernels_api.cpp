@@ -6,6 +6,8 @@
 
 #include "ctm.h"
 #include "ctm_kernels.h"
+#include "adjoint_kernels.hpp"
+#include "chol.hpp"
 #include "gemm.hpp"
 #include "qr.hpp"
 #include "evd.hpp"
@@ -83,6 +85,29 @@ extern "C" int ctm_qr(const double* M_dev, int n, int k, double* Q_dev, double* 
                                                                             k, R_dev);
       CTM_LAUNCHED();
     }
+    CTM_HIP(hipStreamSynchronize(s));
+    return CTM_OK;
+  } catch (const DeviceError& ex) {
+    set_global_error(ex.what());
+    return CTM_EDEVICE;
+  } catch (const std::exception& ex) {
+    set_global_error(ex.what());
+    return CTM_EINVAL;
+  }
+}
+
+extern "C" int ctm_cholesky(const double* G_dev, int k, int m, double* R_dev, double* Rinv_dev,
+                            int* status_host, void* stream) {
+  if (!G_dev || !R_dev || !status_host || k < 1 || k > CHOL_KMAX || m < 1) {
+    set_global_error("ctm_cholesky: bad arguments");
+    return CTM_EINVAL;
+  }
+  try {
+    hipStream_t s = (hipStream_t)stream;
+    DevBuf st(sizeof(int) * 4);
+    launch_cholesky(s, G_dev, k, k, m, R_dev, k, (int*)st.p, nullptr);
+    if (Rinv_dev) launch_tri_inv_upper(s, R_dev, k, k, nullptr, Rinv_dev);
+    CTM_HIP(hipMemcpyAsync(status_host, st.p, sizeof(int), hipMemcpyDeviceToHost, s));
     CTM_HIP(hipStreamSynchronize(s));
     return CTM_OK;
   } catch (const DeviceError& ex) {

@@ -26,14 +26,14 @@ CTM_ENOTCONV = -5
 CTM_ENONFINITE = -6
 CTM_ESTATE = -7
 
-PROJ = {"qr": 0, "evd": 1}
+PROJ = {"qr": 0, "evd": 1, "qr_chol": 2}
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "ladder": 3}
 DTYPE_CODE = {"float64": 0, "float32": 1, "bfloat16": 2}
 
 EXPORTS = ("ctm_symmetrize", "ctm_init", "ctm_step", "ctm_converge", "ctm_energy",
            "ctm_grad", "ctm_spectrum", "ctm_query", "ctm_get_env", "ctm_set_env",
            "ctm_update_tensor", "ctm_set_precision", "ctm_free", "ctm_last_error", "ctm_gemm",
-           "ctm_qr", "ctm_eigh", "ctm_profile", "ctm_profile_read")
+           "ctm_qr", "ctm_cholesky", "ctm_eigh", "ctm_profile", "ctm_profile_read")
 STAGES = ("corner", "projector", "renorm_c", "renorm_t", "big_gemm")
 
 
@@ -72,6 +72,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "ctm_gemm": (i, [i, i, i, i, vp, i64, i, i64, i64, vp, i64, i, i64, i64,
                          vp, i64, i, i64, i64, i, i, d, d, i, vp]),
         "ctm_qr": (i, [vp, i, i, vp, vp, vp]),
+        "ctm_cholesky": (i, [vp, i, i, vp, vp, pi, vp]),
         "ctm_eigh": (i, [vp, i, i, vp, vp, pd, vp]),
         "ctm_profile": (i, [vp, i]),
         "ctm_profile_read": (i, [vp, pd, ctypes.POINTER(i64), pd]),
@@ -138,6 +139,19 @@ def qr(M):
     R = torch.empty((k, k), dtype=torch.float64, device=M.device)
     _check(_lib.ctm_qr(_ptr(M.contiguous()), n, k, _ptr(Q), _ptr(R), _stream()))
     return Q, R
+
+
+def cholesky(G, m):
+    """ctm_cholesky on a (k, k) float64 GPU tensor taken as the Gram matrix of
+    an m-row matrix: (R, R^{-1}, status bits)."""
+    import torch
+    k = G.shape[0]
+    R = torch.empty((k, k), dtype=torch.float64, device=G.device)
+    Ri = torch.empty((k, k), dtype=torch.float64, device=G.device)
+    st = ctypes.c_int(0)
+    _check(_lib.ctm_cholesky(_ptr(G.contiguous()), k, m, _ptr(R), _ptr(Ri), ctypes.byref(st),
+                             _stream()))
+    return R, Ri, st.value
 
 
 def eigh_top(A, k, P=None):

@@ -1,0 +1,188 @@
+"""The Cholesky QR projector (CTM_PROJ_QR_CHOL) on the GPU: the factorization
+kernel against numpy's Cholesky and the shifted-Cholesky rule, and the CTMRG
+iteration with this projector against the CPU oracle (whose Q1 comes from a
+Householder QR) on the same seeded inputs."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import ctm_inputs as ci
+from oracle import ctm as oracle
+from paper_2509_05090_amd import ctm
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda")
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+U = 2.0 ** -53
+
+
+def _matrix(m, k, cond, seed):
+    """m x k matrix with singular values spread geometrically over [1/cond, 1]."""
+    r = np.random.default_rng(seed)
+    Uq, _ = np.linalg.qr(r.standard_normal((m, k)))
+    Vq, _ = np.linalg.qr(r.standard_normal((k, k)))
+    s = np.geomspace(1.0, 1.0 / cond, k)
+    return (Uq * s) @ Vq.T
+
+
+def _shift(m, k, G):
+    return 11.0 * (m * k + k * (k + 1)) * U * np.trace(G)
+
+
+@pytest.mark.parametrize("m,k,cond", [(40, 1, 1.0), (64, 5, 10.0), (500, 33, 1e2), (500, 64, 1e3),
+                                      (5184, 144, 1e2), (5184, 144, 1e6), (800, 192, 1e4)])
+def test_cholesky_well_conditioned(m, k, cond):
+    """G = M^T M with cond(M)^2 well below 1/u: no shift, R^T R = G to
+    rounding, R equal to numpy's factor (positive diagonal), R^{-1} upper
+    triangular with R R^{-1} = I to rounding (k up to the largest order the
+    kernel holds, 192)."""
+    M = _matrix(m, k, cond, m + k)
+    G = M.T @ M
+    R, Ri, st = ctm.cholesky(torch.tensor(G, device=DEV), m)
+    R, Ri = R.cpu().numpy(), Ri.cpu().numpy()
+    assert st == 0
+    assert np.all(np.tril(Ri, -1) == 0.0)
+    assert np.abs(R @ Ri - np.eye(k)).max() < 50 * k * U * cond
+    assert np.all(np.tril(R, -1) == 0.0) and np.all(np.diag(R) > 0)
+    assert np.abs(R.T @ R - G).max() < 50 * k * U * np.abs(G).max()
+    Rn = np.linalg.cholesky(G).T
+    assert np.abs(R - Rn).max() < 1e3 * k * U * cond ** 2 * np.abs(Rn).max()
+
+
+@pytest.mark.parametrize("m,k,cond", [(1000, 50, 1e12), (5184, 144, 1e14)])
+def test_cholesky_shifts_a_numerically_singular_gram_matrix(m, k, cond):
+    """cond(M)^2 far beyond 1/u: the plain factorization breaks down and the
+    kernel factors G + s I with the shifted-Cholesky shift (bit 0)."""
+    M = _matrix(m, k, cond, 7 * k)
+    G = M.T @ M
+    R, _, st = ctm.cholesky(torch.tensor(G, device=DEV), m)
+    R = R.cpu().numpy()
+    assert st == 1
+    Gs = G + _shift(m, k, G) * np.eye(k)
+    assert np.abs(R.T @ R - Gs).max() < 50 * k * U * np.abs(Gs).max()
+
+
+def test_cholesky_rank_deficient_and_zero():
+    """A Gram matrix with zero columns is factored after the shift (its
+    zero pivots become s); an all-zero matrix has s = 0 and is reported as a
+    breakdown (bit 1) with finite clamped pivots."""
+    m, k = 300, 40
+    M = _matrix(m, k, 10.0, 3)
+    M[:, [3, 17, 30]] = 0.0
+    G = M.T @ M
+    R, _, st = ctm.cholesky(torch.tensor(G, device=DEV), m)
+    R = R.cpu().numpy()
+    assert st == 1
+    Gs = G + _shift(m, k, G) * np.eye(k)
+    assert np.abs(R.T @ R - Gs).max() < 50 * k * U * np.abs(Gs).max()
+    R0, Ri0, st0 = ctm.cholesky(torch.zeros((8, 8), dtype=torch.float64, device=DEV), 10)
+    assert st0 == 3 and torch.isfinite(R0).all() and torch.isfinite(Ri0).all()
+
+
+def gpu_context(w, prec="fp64", proj="qr_chol"):
+    A = ctm.symmetrize(torch.tensor(ci.raw_site_tensor(w), device=DEV))
+    G = torch.tensor(ci.start_matrix(w), device=DEV)
+    return ctm.Context(A, G, w.chi, proj=proj, prec=prec)
+
+
+def oracle_state(w):
+    A = oracle.prepare_site_tensor(ci.raw_site_tensor(w))
+    return oracle.State(A, w.chi, ci.start_matrix(w))
+
+
+@pytest.mark.parametrize("D,chi,steps", [(2, 16, 2), (2, 16, 3), (2, 16, 6), (2, 7, 5), (3, 20, 4)])
+def test_chol_steps_match_oracle(D, chi, steps):
+    """First truncation (cond(M) ~ 2e7 for D=2, chi=16) and later steps:
+    gauge-invariant results to rounding, C, T and the projector element by
+    element with the tolerances of the Householder projector's test."""
+    w = ci.Workload("t", 2, D, chi, 100 + D, 200 + chi)
+    c = gpu_context(w)
+    st = oracle_state(w)
+    c.step(steps)
+    st.run(steps=steps)
+    C, T, P = c.get_env()
+    torch.cuda.synchronize()
+    s = c.spectrum()
+    _, rho = c.energy(ci.heisenberg_rotated())
+    c.close()
+    assert np.abs(s - st.spectrum).max() < 1e-10
+    assert np.abs(rho - st.bond_density_matrix()).max() < 1e-11
+    tol = 1e-12 if st.P is None else 1e-8  # no projector yet while chi_c D^2 <= chi
+    assert np.abs(C.cpu().numpy() - st.C).max() < tol
+    assert np.abs(T.cpu().numpy() - st.T).max() < tol
+    if st.P is not None:
+        Ph = P.cpu().numpy()
+        assert np.abs(Ph - st.P).max() < 1e-7
+        assert np.abs(Ph.T @ Ph - np.eye(Ph.shape[1])).max() < 1e-14
+
+
+@pytest.mark.parametrize("key", ["c2", "c4"])
+def test_chol_workload_fp64_matches_oracle(key):
+    """Full workloads in FP64 with the Cholesky projector: the stored oracle
+    run's bond energies to 1e-10 and corner spectrum to 1e-9."""
+    w = ci.WORKLOADS[key]
+    gold = json.load(open(os.path.join(GOLDEN, f"{key}_qr.json")))
+    c = gpu_context(w)
+    c.step(gold["steps"])
+    for name, h in ci.bond_operators(w).items():
+        e, _ = c.energy(h)
+        assert abs(e - gold["e_bond"][name]) < 1e-10, (name, e, gold["e_bond"][name])
+    s = c.spectrum()
+    c.close()
+    assert np.abs(s - np.array(gold["spectrum"])).max() < 1e-9
+
+
+def test_chol_projector_equals_householder_projector():
+    """The two projectors agree to rounding step by step (same span, same
+    basis rule)."""
+    w = ci.Workload("t", 2, 3, 30, 401, 402)
+    a, b = gpu_context(w, proj="qr_chol"), gpu_context(w, proj="qr")
+    for _ in range(4):
+        a.step(2)
+        b.step(2)
+        _, _, Pa = a.get_env()
+        _, _, Pb = b.get_env()
+        assert (Pa - Pb).abs().max().item() < 1e-9
+    a.close()
+    b.close()
+
+
+def test_chol_c3_one_step_fp64_matches_oracle():
+    """5184 x 5184 enlarged corner: one FP64 step with the Cholesky projector
+    from a full-size state against the oracle's step from the same state."""
+    w = ci.WORKLOADS["c3"]
+    c = gpu_context(w)
+    c.step(6)
+    C, T, P = c.get_env()
+    st = oracle_state(w)
+    st.C, st.T, st.P = C.cpu().numpy(), T.cpu().numpy(), P.cpu().numpy()
+    c.step(1)
+    st.step()
+    C, T, P = c.get_env()
+    s = c.spectrum()
+    _, rho = c.energy(ci.heisenberg_rotated())
+    c.close()
+    Ph = P.cpu().numpy()
+    assert np.abs(s - st.spectrum).max() < 1e-12
+    assert np.abs(rho - st.bond_density_matrix()).max() < 1e-12
+    assert np.abs(C.cpu().numpy() - st.C).max() < 1e-10
+    assert np.abs(T.cpu().numpy() - st.T).max() < 1e-10
+    assert np.abs(Ph - st.P).max() < 1e-9
+    assert np.abs(Ph.T @ Ph - np.eye(w.chi)).max() < 1e-14
+
+
+def test_chol_c3_fp32_converged_energy():
+    """FP32 contractions with the Cholesky projector on the headline
+    workload: converged site energy within 1e-6 of the oracle's FP64 run."""
+    w = ci.WORKLOADS["c3"]
+    gold = json.load(open(os.path.join(GOLDEN, "c3_qr.json")))
+    c = gpu_context(w, prec="fp32")
+    steps, delta, ok = c.converge(1e-8, 3000, n_check=10)
+    e, _ = c.energy(ci.site_energy_operator(w))
+    c.close()
+    print(f"c3 fp32 cholesky: {steps} steps, |dE| = {abs(e - gold['e_site']):.3e}")
+    assert ok
+    assert abs(e - gold["e_site"]) < 1e-6
