@@ -292,7 +292,7 @@ def main():
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--modes", default="fp32,fp64,bf16")
-    ap.add_argument("--proj", default="qr", choices=("qr", "qr_chol"),
+    ap.add_argument("--proj", default="qr_chol", choices=("qr", "qr_chol"),
                     help="QR projector: Q1 by Householder (qr) or by Cholesky QR (qr_chol)")
     ap.add_argument("--no-large", action="store_true", help="skip the D=8, chi=256 leg")
     ap.add_argument("--no-projectors", action="store_true",
@@ -357,6 +357,15 @@ def main():
                 r["oracle_steps"] = gold["steps"]
         res[prec] = r
         log(f"[bench] {prec}: {json.dumps(r)}")
+
+    householder = None
+    if args.proj == "qr_chol" and "fp32" in modes:
+        log("[bench] fp32 with the Householder projector, for comparison")
+        hrate, _, hstages, _ = gpu_rate(ctm, torch, A, G, w.chi, "fp32", args.warmup, args.steps,
+                                        proj="qr")
+        householder = {"fp32_iters_per_s": hrate,
+                       "stage_ms_per_step": {k: v[0] / 10 for k, v in hstages.items()}}
+        log(f"[bench] householder: {json.dumps(householder)}")
 
     ladder = None
     if not args.no_converge:
@@ -433,10 +442,12 @@ def main():
                    "d": w.d, "D": w.D, "chi": w.chi, "n": w.n,
                    "precision": "contractions FP32 matrix cores (FP32 accumulate); "
                                 "QR, basis, normalization, energy FP64",
-                   "qr": "Cholesky QR (3 passes)" if args.proj == "qr_chol" else "Householder"},
+                   "qr": "Q1 by Cholesky QR (3 passes), gs(X) by Householder"
+                         if args.proj == "qr_chol" else "Householder"},
         "modes": res,
         "speedup_mixed_vs_fp64": (res["fp32"]["iters_per_s"] / res["fp64"]["iters_per_s"])
         if "fp32" in res and "fp64" in res else None,
+        "householder_projector": householder,
         "ladder": ladder,
         "gradient": grad,
         "large": large,

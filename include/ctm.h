@@ -64,14 +64,15 @@ enum {
  *               on the GPU; the baseline the QR projector replaces.  Needs
  *               chi*D^2 <= 8192; synchronizes once per step.
  * CTM_PROJ_QR_CHOL: the CTM_PROJ_QR rule with Q1 from three Cholesky QR
- *               passes (Gram matrix on the matrix cores, Cholesky of the
- *               chi x chi Gram matrix, Q1 <- Q1 R^{-1}), the first on
+ *               passes (Gram matrix on the matrix cores, blocked Cholesky of
+ *               the chi x chi Gram matrix and the inverse of its factor,
+ *               Q1 <- Q1 R^{-1}; gs(X) as in CTM_PROJ_QR), the first on
  *               M^T M + s I when M^T M is numerically singular (shifted
  *               Cholesky QR, Fukaya et al., SIAM J. Sci. Comput. 42 (2020)).
  *               Q depends on Q1 only through span(M), so it agrees with
  *               CTM_PROJ_QR to rounding while cond(M) stays below about 1e15;
  *               a Gram matrix that breaks down even when shifted sets the
- *               non-finite flag (CTM_ENONFINITE).  Needs chi <= 192. */
+ *               non-finite flag (CTM_ENONFINITE).  Needs chi <= 144. */
 typedef enum { CTM_PROJ_QR = 0, CTM_PROJ_EVD = 1, CTM_PROJ_QR_CHOL = 2 } ctm_proj;
 
 /* Arithmetic of the contractions.  The QR, the sign gauge, the

@@ -41,7 +41,7 @@ int ctm_gemm(int prec, int M, int N, int K,
 int ctm_qr(const double *M_dev, int n, int k, double *Q_dev, double *R_dev, void *stream);
 
 /* Cholesky factorization G = R^T R of the symmetric k x k FP64 matrix G_dev
- * (row-major, lower triangle read; 1 <= k <= 192), taken as the Gram matrix
+ * (row-major, lower triangle read; 1 <= k <= 144), taken as the Gram matrix
  * of an m x k matrix: the factor of the Cholesky QR projector
  * (CTM_PROJ_QR_CHOL), by one workgroup.  R_dev (k x k) receives the upper
  * triangle with a positive diagonal, zeros below; Rinv_dev (k x k, nullable)

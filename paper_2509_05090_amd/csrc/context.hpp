@@ -53,8 +53,8 @@ struct ctm_ctx {
   double *M = nullptr, *MP = nullptr, *Q = nullptr, *Cp = nullptr, *Tp = nullptr, *Xs = nullptr, *Xq = nullptr;
   double *sgn = nullptr, *sumsq = nullptr, *dev_small = nullptr;
   int* flag = nullptr;
-  // Cholesky QR projector: Gram matrix, its factor and inverse, X = Q1^T P_prev
-  double *cg = nullptr, *cr = nullptr, *cri = nullptr, *cx = nullptr;
+  // Cholesky QR projector: Gram matrix, inverse of its factor, X = Q1^T P_prev
+  double *cg = nullptr, *cri = nullptr, *cx = nullptr;
   int* chol_status = nullptr;
   // Intermediates; allocated with 8-byte elements so that they hold any precision.
   void *aE = nullptr, *CE = nullptr, *TE = nullptr, *PE = nullptr, *QE = nullptr;

@@ -41,7 +41,6 @@
 #include <vector>
 
 #include "ctm.h"
-#include "adjoint_kernels.hpp"
 #include "chol.hpp"
 #include "gemm.hpp"
 #include "kernels.hpp"
@@ -257,8 +256,7 @@ void chol_pass(ctm_ctx* c, const double* In, double* Out, int n, int chi) {
   hipStream_t s = c->stream;
   gemm(s, DType::F64, chi, chi, n, Operand{In, chi, true}, Operand{In, chi, false},
        Output{c->cg, chi, DType::F64}, 1, 1, 1.0, 0.0, c->ws);
-  launch_cholesky(s, c->cg, chi, chi, n, c->cr, chi, c->chol_status, c->flag);
-  launch_tri_inv_upper(s, c->cr, chi, chi, nullptr, c->cri);
+  launch_cholesky(s, c->cg, chi, chi, n, nullptr, 0, c->cri, chi, c->chol_status, c->flag);
   gemm(s, DType::F64, n, chi, chi, Operand{In, chi, false}, Operand{c->cri, chi, false},
        Output{Out, chi, DType::F64}, 1, 1, 1.0, 0.0, c->ws);
 }
@@ -268,7 +266,8 @@ void chol_pass(ctm_ctx* c, const double* In, double* Out, int n, int chi) {
 // orthonormal basis of span(M) to working precision for cond(M) below about
 // 1/u.  The isometry Q = Q1 gs(Q1^T P_prev) depends on Q1 only through
 // span(Q1) = span(M), so it is the same as with the Householder Q1 up to
-// rounding.
+// rounding.  gs(X) stays a Householder QR: for the chi x chi matrix X that
+// is cheaper than three more Cholesky passes.
 const double* chol_projector(ctm_ctx* c, DType e, bool update) {
   hipStream_t s = c->stream;
   const int chi = c->chi;
@@ -562,7 +561,6 @@ void allocate(ctm_ctx* c) {
   c->Xq = c->allocd(chi * chi);
   if (c->cfg.proj == CTM_PROJ_QR_CHOL) {
     c->cg = c->allocd(chi * chi);
-    c->cr = c->allocd(chi * chi);
     c->cri = c->allocd(chi * chi);
     c->cx = c->allocd(chi * chi);
     c->chol_status = (int*)c->alloc(sizeof(int) * 4);

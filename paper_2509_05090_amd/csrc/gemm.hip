@@ -825,7 +825,10 @@ void gemm(hipStream_t s, DType e, int M, int N, int K, const Operand& A, const O
   const DType acc_t = e == DType::F64 ? DType::F64 : DType::F32;
   bool split = ksplit > 1 || C.t != e || sumsq != nullptr;
   if (!batched && ksplit == 0 && tiles < 1024) {
-    const int want = (int)std::min<int64_t>(MAX_SPLIT, std::max<int64_t>(1, 1024 / tiles));
+    // small outputs (Gram matrices) take up to 64 k-splits when the scratch
+    // holds them
+    const int cap = (int64_t)M * N <= 65536 ? 64 : MAX_SPLIT;
+    const int want = (int)std::min<int64_t>(cap, std::max<int64_t>(1, 1024 / tiles));
     const int maxk = (int)std::max<int64_t>(1, cdiv(K, 4 * BK));
     const int fit = (int)std::max<int64_t>(
         1, (int64_t)(ws.bytes / ((size_t)M * N * dtype_size(acc_t))));

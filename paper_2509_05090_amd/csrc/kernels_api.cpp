@@ -6,7 +6,6 @@
 
 #include "ctm.h"
 #include "ctm_kernels.h"
-#include "adjoint_kernels.hpp"
 #include "chol.hpp"
 #include "gemm.hpp"
 #include "qr.hpp"
@@ -105,8 +104,7 @@ extern "C" int ctm_cholesky(const double* G_dev, int k, int m, double* R_dev, do
   try {
     hipStream_t s = (hipStream_t)stream;
     DevBuf st(sizeof(int) * 4);
-    launch_cholesky(s, G_dev, k, k, m, R_dev, k, (int*)st.p, nullptr);
-    if (Rinv_dev) launch_tri_inv_upper(s, R_dev, k, k, nullptr, Rinv_dev);
+    launch_cholesky(s, G_dev, k, k, m, R_dev, k, Rinv_dev, k, (int*)st.p, nullptr);
     CTM_HIP(hipMemcpyAsync(status_host, st.p, sizeof(int), hipMemcpyDeviceToHost, s));
     CTM_HIP(hipStreamSynchronize(s));
     return CTM_OK;

@@ -33,12 +33,13 @@ def _shift(m, k, G):
 
 
 @pytest.mark.parametrize("m,k,cond", [(40, 1, 1.0), (64, 5, 10.0), (500, 33, 1e2), (500, 64, 1e3),
-                                      (5184, 144, 1e2), (5184, 144, 1e6), (800, 192, 1e4)])
+                                      (5184, 144, 1e2), (5184, 144, 1e6), (800, 144, 1e4),
+                                      (300, 100, 1e3)])
 def test_cholesky_well_conditioned(m, k, cond):
     """G = M^T M with cond(M)^2 well below 1/u: no shift, R^T R = G to
     rounding, R equal to numpy's factor (positive diagonal), R^{-1} upper
-    triangular with R R^{-1} = I to rounding (k up to the largest order the
-    kernel holds, 192)."""
+    triangular with R R^{-1} = I to rounding (k = 1 .. 144, the largest order
+    the kernel holds; orders that are not multiples of its 16-wide blocks)."""
     M = _matrix(m, k, cond, m + k)
     G = M.T @ M
     R, Ri, st = ctm.cholesky(torch.tensor(G, device=DEV), m)
