@@ -294,6 +294,8 @@ def main():
     ap.add_argument("--modes", default="fp32,fp64,bf16")
     ap.add_argument("--proj", default="qr_chol", choices=("qr", "qr_chol"),
                     help="QR projector: Q1 by Householder (qr) or by Cholesky QR (qr_chol)")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the FP32 rate with the Householder projector")
     ap.add_argument("--no-large", action="store_true", help="skip the D=8, chi=256 leg")
     ap.add_argument("--no-projectors", action="store_true",
                     help="skip the QR vs eigendecomposition leg (D=5, chi=120)")
@@ -359,7 +361,7 @@ def main():
         log(f"[bench] {prec}: {json.dumps(r)}")
 
     householder = None
-    if args.proj == "qr_chol" and "fp32" in modes:
+    if args.proj == "qr_chol" and "fp32" in modes and not args.no_compare:
         log("[bench] fp32 with the Householder projector, for comparison")
         hrate, _, hstages, _ = gpu_rate(ctm, torch, A, G, w.chi, "fp32", args.warmup, args.steps,
                                         proj="qr")
