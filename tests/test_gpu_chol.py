@@ -187,3 +187,23 @@ def test_chol_c3_fp32_converged_energy():
     print(f"c3 fp32 cholesky: {steps} steps, |dE| = {abs(e - gold['e_site']):.3e}")
     assert ok
     assert abs(e - gold["e_site"]) < 1e-6
+
+
+def test_chol_fixed_point_gradient_equals_householder():
+    """D=4, chi=100 Kitaev-Heisenberg workload converged with each QR
+    projector: the same fixed point, so ctm_grad's fixed-point gradient (whose
+    adjoint tape factors with Householder) agrees to the adjoint tolerance."""
+    w = ci.WORKLOADS["c4"]
+    h = ci.site_energy_operator(w)
+    out = {}
+    for proj in ("qr", "qr_chol"):
+        c = gpu_context(w, proj=proj)
+        c.converge(1e-14, 6000, n_check=20)
+        g, e, iters, ok = c.grad(h, mode=0, tol=1e-13, max_iter=5000)
+        c.close()
+        assert ok
+        out[proj] = (g.cpu().numpy(), e)
+    ga, ea = out["qr"]
+    gb, eb = out["qr_chol"]
+    assert abs(ea - eb) < 1e-12
+    assert np.abs(ga - gb).max() < 1e-8 * np.abs(ga).max()
