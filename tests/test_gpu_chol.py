@@ -120,7 +120,7 @@ def test_chol_steps_match_oracle(D, chi, steps):
         assert np.abs(Ph.T @ Ph - np.eye(Ph.shape[1])).max() < 1e-14
 
 
-@pytest.mark.parametrize("key", ["c2", "c4"])
+@pytest.mark.parametrize("key", ["c1", "c2", "c4"])
 def test_chol_workload_fp64_matches_oracle(key):
     """Full workloads in FP64 with the Cholesky projector: the stored oracle
     run's bond energies to 1e-10 and corner spectrum to 1e-9."""
