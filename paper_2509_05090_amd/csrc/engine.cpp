@@ -246,7 +246,7 @@ const double* qr_projector(ctm_ctx* c, DType e, bool update) {
   // projector goes straight into its place
   double* Qout = update ? c->P : c->Q;
   gemm(s, DType::F64, n, chi, chi, Operand{c->M, chi, false}, Operand{c->Xq, chi, false},
-       Output{Qout, chi, DType::F64}, 1, 1, 1.0, 0.0, c->ws);
+       Output{Qout, chi, DType::F64}, 1, 1, 1.0, 0.0, c->ws, 1);
   return Qout;
 }
 
@@ -258,7 +258,7 @@ void chol_pass(ctm_ctx* c, const double* In, double* Out, int n, int chi) {
        Output{c->cg, chi, DType::F64}, 1, 1, 1.0, 0.0, c->ws);
   launch_cholesky(s, c->cg, chi, chi, n, nullptr, 0, c->cri, chi, c->chol_status, c->flag);
   gemm(s, DType::F64, n, chi, chi, Operand{In, chi, false}, Operand{c->cri, chi, false},
-       Output{Out, chi, DType::F64}, 1, 1, 1.0, 0.0, c->ws);
+       Output{Out, chi, DType::F64}, 1, 1, 1.0, 0.0, c->ws, 1);
 }
 
 // The QR projector with Q1 from Cholesky QR instead of Householder: three
@@ -299,7 +299,7 @@ const double* chol_projector(ctm_ctx* c, DType e, bool update) {
   gram_schmidt_small(c, c->cx, chi, chi, c->Xq);
   double* Qout = update ? c->P : c->Q;
   gemm(s, DType::F64, n, chi, chi, Operand{c->M, chi, false}, Operand{c->Xq, chi, false},
-       Output{Qout, chi, DType::F64}, 1, 1, 1.0, 0.0, c->ws);
+       Output{Qout, chi, DType::F64}, 1, 1, 1.0, 0.0, c->ws, 1);
   return Qout;
 }
 
