@@ -52,11 +52,20 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def run_stream(torch, proj):
+    """Stream context for a run: the Cholesky projector overlaps work on
+    CU-masked streams of its own, which needs the library's stream to be a
+    stream other than the legacy default one (blocking streams synchronize
+    with it); the Householder projector runs on the default stream."""
+    import contextlib
+    return torch.cuda.stream(torch.cuda.Stream()) if proj == "qr_chol" else contextlib.nullcontext()
+
+
 def gpu_rate(ctm, torch, A, G, chi, prec, warmup, steps, n_check=10, proj="qr"):
     """Steps/s of `steps` timed steps after `warmup` untimed ones (from the
     truncated regime), also with the corner-spectrum check every n_check
     steps, and the stage profile of 10 further steps."""
-    with ctm.Context(A, G, chi, proj=proj, prec=prec) as c:
+    with run_stream(torch, proj), ctm.Context(A, G, chi, proj=proj, prec=prec) as c:
         c.step(max(warmup, 3))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -88,7 +97,7 @@ def gpu_converged(ctm, torch, A, G, chi, prec, tol, max_steps, h, residuals=None
     workloads: its spectrum comes in +-lambda pairs and C keeps turning
     within their two-dimensional eigenspaces (the oracle does the same),
     while its spectrum, T, P and the energy converge."""
-    with ctm.Context(A, G, chi, proj=proj, prec=prec) as c:
+    with run_stream(torch, proj), ctm.Context(A, G, chi, proj=proj, prec=prec) as c:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         steps, delta, ok = c.converge(tol, max_steps, n_check=10)

@@ -72,7 +72,13 @@ enum {
  *               Q depends on Q1 only through span(M), so it agrees with
  *               CTM_PROJ_QR to rounding while cond(M) stays below about 1e15;
  *               a Gram matrix that breaks down even when shifted sets the
- *               non-finite flag (CTM_ENONFINITE).  Needs chi <= 144. */
+ *               non-finite flag (CTM_ENONFINITE).  Needs chi <= 144.
+ *               On a stream other than the NULL stream, FP64 and FP32 update
+ *               steps form Ct Q1 and V Q1 on two CU-masked streams of the
+ *               context (16 CUs factor X, the rest multiply) and finish the
+ *               renormalization with (Ct Q1) gs(X) and (V Q1) gs(X); on the
+ *               NULL stream (which synchronizes with such streams) the steps
+ *               run in sequence.  Same result to rounding either way. */
 typedef enum { CTM_PROJ_QR = 0, CTM_PROJ_EVD = 1, CTM_PROJ_QR_CHOL = 2 } ctm_proj;
 
 /* Arithmetic of the contractions.  The QR, the sign gauge, the

@@ -32,6 +32,17 @@ struct ctm_ctx {
   // the basis matrix is factored on `stream`), joined by ev_fork / ev_join
   hipStream_t stream2 = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // Cholesky QR projector, update steps (FP64, FP32): while the basis matrix
+  // X is factored on stream_small (a few CUs), the products Ct Q1 and V Q1
+  // run on stream_big (the other CUs); disjoint CU masks keep the
+  // latency-bound factorization off the products' CUs.  overlap is false if
+  // the masked streams are unavailable.
+  hipStream_t stream_big = nullptr, stream_small = nullptr;
+  hipEvent_t ev_big = nullptr, ev_small = nullptr;
+  bool overlap = false;
+  bool pre_q1 = false;  // G1 = Ct Q1 and W1 = V Q1 pending for the renormalization
+  double *G1 = nullptr, *W1 = nullptr;
+  Scratch ws_big;  // split-K scratch of the products on stream_big
   // convergence test: pinned host copy of the corner taken before a batch's
   // last step, and the event marking the copy
   double* hostC = nullptr;
@@ -113,6 +124,13 @@ struct ctm_ctx {
       (void)hipStreamSynchronize(stream2);
       (void)hipStreamDestroy(stream2);
     }
+    for (hipStream_t* q : {&stream_big, &stream_small})
+      if (*q) {
+        (void)hipStreamSynchronize(*q);
+        (void)hipStreamDestroy(*q);
+      }
+    if (ev_big) (void)hipEventDestroy(ev_big);
+    if (ev_small) (void)hipEventDestroy(ev_small);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
     if (ev_spec) (void)hipEventDestroy(ev_spec);

@@ -188,8 +188,9 @@ void enlarged_corner(ctm_ctx* c, DType e) {
 // Gram-Schmidt basis of the columns of the k x k matrix X (leading
 // dimension ld; QR with a positive diagonal of R), into Qx (ld k).  X is
 // overwritten.  Uses the second QR workspace.
-void gram_schmidt_small(ctm_ctx* c, double* X, int ld, int k, double* Qx) {
-  hipStream_t s = c->stream;
+void gram_schmidt_small(ctm_ctx* c, double* X, int ld, int k, double* Qx,
+                        hipStream_t s = nullptr) {
+  if (!s) s = c->stream;
   householder_qr(s, X, ld, k, k, c->qr2);
   householder_form_q(s, c->qr2, k, k, Qx, k);
   launch_diag_signs(s, X, ld, k, c->sgn);
@@ -296,7 +297,29 @@ const double* chol_projector(ctm_ctx* c, DType e, bool update) {
   // basis: Q = Q1 gs(X), X = Q1^T P_prev
   gemm(s, DType::F64, chi, chi, n, Operand{c->M, chi, true}, Operand{Pref, chi, false},
        Output{c->cx, chi, DType::F64}, 1, 1, 1.0, 0.0, c->ws);
-  gram_schmidt_small(c, c->cx, chi, chi, c->Xq);
+  if (update && c->overlap && e != DType::BF16) {
+    // G1 = Ct Q1 and W1 = V Q1 on the products' CUs while gs(X) runs on the
+    // reserved ones; the renormalization finishes Gm = G1 Qx and V2 = W1 Qx
+    CTM_HIP(hipEventRecord(c->ev_fork, s));
+    CTM_HIP(hipStreamWaitEvent(c->stream_big, c->ev_fork, 0));
+    CTM_HIP(hipStreamWaitEvent(c->stream_small, c->ev_fork, 0));
+    hipStream_t sb = c->stream_big;
+    launch_cast_transpose(sb, c->M, c->W, e, n, chi);
+    KernelEvents ev1, ev2;
+    gemm(sb, e, n, chi, n, Operand{c->Ct, n, false}, Operand{c->W, n, true},
+         Output{c->G1, chi, e}, 1, 1, 1.0, 0.0, c->ws_big, 0, nullptr,
+         big_gemm_events(c, ev1, n, chi, n));
+    gemm(sb, e, n, chi, n, Operand{c->V, n, false}, Operand{c->W, n, true},
+         Output{c->W1, chi, e}, 1, 1, 1.0, 0.0, c->ws_big, 0, nullptr,
+         big_gemm_events(c, ev2, n, chi, n));
+    CTM_HIP(hipEventRecord(c->ev_big, sb));
+    gram_schmidt_small(c, c->cx, chi, chi, c->Xq, c->stream_small);
+    CTM_HIP(hipEventRecord(c->ev_small, c->stream_small));
+    CTM_HIP(hipStreamWaitEvent(s, c->ev_small, 0));
+    c->pre_q1 = true;
+  } else {
+    gram_schmidt_small(c, c->cx, chi, chi, c->Xq);
+  }
   double* Qout = update ? c->P : c->Q;
   gemm(s, DType::F64, n, chi, chi, Operand{c->M, chi, false}, Operand{c->Xq, chi, false},
        Output{Qout, chi, DType::F64}, 1, 1, 1.0, 0.0, c->ws, 1);
@@ -356,10 +379,24 @@ void step_once(ctm_ctx* c) {
   void* QT = c->QE;
   launch_cast_transpose(s, Qp, QT, e, (int)n, xn);
   KernelEvents ev1, ev2;
+  const bool pre = c->pre_q1;  // Gm = (Ct Q1) Qx and V2 = (V Q1) Qx
+  c->pre_q1 = false;
+  const void* QxE = c->Xq;
+  if (pre) {
+    CTM_HIP(hipStreamWaitEvent(s, c->ev_big, 0));
+    if (e != DType::F64) {
+      launch_cast(s, c->Xq, c->cg, e, (int64_t)xn * xn);
+      QxE = c->cg;
+    }
+  }
   // 6. Gm = Ct Q
-  gemm(s, e, (int)n, xn, (int)n, Operand{c->Ct, n, false}, Operand{QT, n, true},
-       Output{c->Gm, xn, e}, 1, 1, 1.0, 0.0, c->ws, 0, nullptr,
-       big_gemm_events(c, ev1, n, xn, n));
+  if (pre)
+    gemm(s, e, (int)n, xn, xn, Operand{c->G1, xn, false}, Operand{QxE, xn, false},
+         Output{c->Gm, xn, e}, 1, 1, 1.0, 0.0, c->ws, 1);
+  else
+    gemm(s, e, (int)n, xn, (int)n, Operand{c->Ct, n, false}, Operand{QT, n, true},
+         Output{c->Gm, xn, e}, 1, 1, 1.0, 0.0, c->ws, 0, nullptr,
+         big_gemm_events(c, ev1, n, xn, n));
   // 7. C' = Q^T Gm, symmetrized and normalized
   gemm(s, e, xn, xn, (int)n, Operand{QT, n, false}, Operand{c->Gm, xn, false},
        Output{c->Cp, xn, DType::F64}, 1, 1, 1.0, 0.0, c->ws);
@@ -367,9 +404,13 @@ void step_once(ctm_ctx* c) {
   stage_end(c, CTM_STAGE_RENORM_C);
   stage_begin(c, CTM_STAGE_RENORM_T);
   // 8. V2 = V Q
-  gemm(s, e, (int)n, xn, (int)n, Operand{c->V, n, false}, Operand{QT, n, true},
-       Output{c->V2, xn, e}, 1, 1, 1.0, 0.0, c->ws, 0, nullptr,
-       big_gemm_events(c, ev2, n, xn, n));
+  if (pre)
+    gemm(s, e, (int)n, xn, xn, Operand{c->W1, xn, false}, Operand{QxE, xn, false},
+         Output{c->V2, xn, e}, 1, 1, 1.0, 0.0, c->ws, 1);
+  else
+    gemm(s, e, (int)n, xn, (int)n, Operand{c->V, n, false}, Operand{QT, n, true},
+         Output{c->V2, xn, e}, 1, 1, 1.0, 0.0, c->ws, 0, nullptr,
+         big_gemm_events(c, ev2, n, xn, n));
   // 9. V3 stored transposed, V3t[(l,nu)][(alpha,k)] = sum_m a[k][l][m] V2[(alpha,m)][nu],
   //    into the Ct buffer (Ct is no longer needed): batches (alpha, l) of
   //    xn x D2 x D2 products, A[alpha](nu, m) = V2[alpha][m][nu],
@@ -563,6 +604,31 @@ void allocate(ctm_ctx* c) {
     c->cg = c->allocd(chi * chi);
     c->cri = c->allocd(chi * chi);
     c->cx = c->allocd(chi * chi);
+    c->G1 = c->allocd(nmax * chi);
+    c->W1 = c->allocd(nmax * chi);
+    c->ws_big = Scratch{c->alloc(gemm_scratch_bytes(DType::F64, (int)nmax, (int)chi)),
+                        gemm_scratch_bytes(DType::F64, (int)nmax, (int)chi)};
+    // CU masks: the first 16 CUs for the basis factorization, the rest for
+    // the products.  Streams made with a CU mask are blocking streams, which
+    // the legacy default stream would synchronize with at every launch, so
+    // with the null stream (or no masked streams) there is no overlap.
+    int dev = 0, ncu = 0;
+    CTM_HIP(hipGetDevice(&dev));
+    CTM_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    if (c->stream != nullptr && ncu >= 64) {
+      std::vector<uint32_t> small((ncu + 31) / 32, 0u), big((ncu + 31) / 32, 0u);
+      for (int i = 0; i < ncu; ++i) (i < 16 ? small : big)[i / 32] |= 1u << (i % 32);
+      if (hipExtStreamCreateWithCUMask(&c->stream_small, (uint32_t)small.size(), small.data()) ==
+              hipSuccess &&
+          hipExtStreamCreateWithCUMask(&c->stream_big, (uint32_t)big.size(), big.data()) ==
+              hipSuccess) {
+        CTM_HIP(hipEventCreateWithFlags(&c->ev_big, hipEventDisableTiming | hipEventDisableSystemFence));
+        CTM_HIP(hipEventCreateWithFlags(&c->ev_small, hipEventDisableTiming | hipEventDisableSystemFence));
+        c->overlap = true;
+      } else {
+        (void)hipGetLastError();
+      }
+    }
     c->chol_status = (int*)c->alloc(sizeof(int) * 4);
   }
   c->Tp = c->allocd(chi * D2 * chi);
@@ -585,7 +651,11 @@ void allocate(ctm_ctx* c) {
                         (int)chi);
   c->qr2 = qr_work_carve(c->stream, c->alloc(qr_work_bytes((int)chi, (int)chi)), (int)chi,
                          (int)chi);
-  CTM_HIP(hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking));
+  // the Householder projector's second stream (the Cholesky projector has
+  // its own pair below); every stream a context creates takes a hardware
+  // queue of the process's few
+  if (c->cfg.proj != CTM_PROJ_QR_CHOL)
+    CTM_HIP(hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking));
   // fork/join of the projector's two streams: an ordering within the device,
   // so no system-scope fence (host and other devices never read through them)
   CTM_HIP(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming | hipEventDisableSystemFence));

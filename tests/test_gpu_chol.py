@@ -207,3 +207,68 @@ def test_chol_fixed_point_gradient_equals_householder():
     gb, eb = out["qr_chol"]
     assert abs(ea - eb) < 1e-12
     assert np.abs(ga - gb).max() < 1e-8 * np.abs(ga).max()
+
+
+def test_chol_overlapped_products_match_the_sequential_path():
+    """On a stream other than the default one the Cholesky projector forms
+    Ct Q1 and V Q1 beside the basis factorization (CU-masked streams) and
+    finishes Gm = (Ct Q1) Qx, V2 = (V Q1) Qx: the environment agrees with the
+    sequential path (default stream) to rounding in FP64, and both match the
+    oracle's steps."""
+    w = ci.Workload("t", 2, 3, 20, 501, 502)
+    c = gpu_context(w)
+    c.step(8)
+    C0, T0, P0 = c.get_env()
+    c.close()
+    with torch.cuda.stream(torch.cuda.Stream()):
+        d = gpu_context(w)
+        d.step(8)
+        C1, T1, P1 = d.get_env()
+        torch.cuda.synchronize()
+        d.close()
+    st = oracle_state(w)
+    st.run(steps=8)
+    for a, b in ((C0, C1), (T0, T1), (P0, P1)):
+        assert (a - b).abs().max().item() < 1e-12
+    assert np.abs(C1.cpu().numpy() - st.C).max() < 1e-8
+    assert np.abs(T1.cpu().numpy() - st.T).max() < 1e-8
+
+
+def test_chol_overlapped_c3_one_step_fp64_matches_oracle():
+    """The overlapped path at full size: one FP64 step from a full-size state
+    against the oracle's step from the same state."""
+    w = ci.WORKLOADS["c3"]
+    with torch.cuda.stream(torch.cuda.Stream()):
+        c = gpu_context(w)
+        c.step(6)
+        C, T, P = c.get_env()
+        st = oracle_state(w)
+        st.C, st.T, st.P = C.cpu().numpy(), T.cpu().numpy(), P.cpu().numpy()
+        c.step(1)
+        C, T, P = c.get_env()
+        s = c.spectrum()
+        _, rho = c.energy(ci.heisenberg_rotated())
+        torch.cuda.synchronize()
+        c.close()
+    st.step()
+    assert np.abs(s - st.spectrum).max() < 1e-12
+    assert np.abs(rho - st.bond_density_matrix()).max() < 1e-12
+    assert np.abs(C.cpu().numpy() - st.C).max() < 1e-10
+    assert np.abs(T.cpu().numpy() - st.T).max() < 1e-10
+    assert np.abs(P.cpu().numpy() - st.P).max() < 1e-9
+
+
+def test_chol_overlapped_fp32_energy():
+    """FP32 on the overlapped path: converged site energy of the headline
+    workload within 1e-6 of the oracle's FP64 run."""
+    w = ci.WORKLOADS["c3"]
+    gold = json.load(open(os.path.join(GOLDEN, "c3_qr.json")))
+    with torch.cuda.stream(torch.cuda.Stream()):
+        c = gpu_context(w, prec="fp32")
+        steps, delta, ok = c.converge(1e-8, 3000, n_check=10)
+        e, _ = c.energy(ci.site_energy_operator(w))
+        torch.cuda.synchronize()
+        c.close()
+    print(f"c3 fp32 overlapped: {steps} steps, |dE| = {abs(e - gold['e_site']):.3e}")
+    assert ok
+    assert abs(e - gold["e_site"]) < 1e-6
