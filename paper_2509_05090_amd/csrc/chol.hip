@@ -3,8 +3,8 @@
 //
 // The lower block triangle of L = R^T sits in LDS as 16 x 16 blocks (rows
 // padded to 17 doubles).  For block column J: wavefront 0 factors the
-// diagonal block (unblocked, column by column, wavefront-synchronous) and
-// inverts it; then every wavefront takes blocks of the panel,
+// diagonal block (unblocked, column by column, in registers with lane
+// shuffles) and inverts it; then every wavefront takes blocks of the panel,
 // L_IJ = A_IJ L_JJ^{-T}, and of the trailing update, A_IK -= L_IJ L_KJ^T,
 // each a 16 x 16 x 16 product on the FP64 matrix cores (v_mfma_f64_16x16x4,
 // four per block).  The inverse X = L^{-1} follows block row by block row:
@@ -34,6 +34,7 @@ constexpr int LDB = 17;                    // padded row length of a block in LD
 constexpr int BSZ = CB * LDB;              // doubles per block
 constexpr int NBMAX = CHOL_KMAX / CB;      // blocks per dimension
 constexpr int NBLK = NBMAX * (NBMAX + 1) / 2;
+static_assert(NBMAX == 9 && CT == 256, "the inverse's work split assumes 9 block rows, 4 wavefronts");
 
 __device__ __forceinline__ int bidx(int I, int J) { return (I * (I + 1)) / 2 + J; }  // J <= I
 
@@ -130,38 +131,58 @@ __global__ __launch_bounds__(CT) void cholesky_kernel(const double* __restrict__
       double* D = A + bidx(J, J) * BSZ;
       double* Di = Dinv + J * BSZ;
       if (wv == 0) {
-        // diagonal block: right-looking, one column per step; lane (q, i)
-        // updates row i at columns q, q + 4, q + 8, q + 12
+        // diagonal block in registers, right-looking, one column per step:
+        // lane (q, i) holds row i at columns 4 q .. 4 q + 3; the pivot is
+        // read from its lane and the column's multipliers are broadcast
+        // with lane shuffles, so a column costs no LDS round trip
         const int i = r16, q = grp;
-        double rinv[CB];
-        for (int j = 0; j < CB; ++j) {
-          double d = D[j * LDB + j];
-          const double lim = 64.0 * u * dref[J * CB + j];
-          if (!(d > lim) || !(d <= 1.7e308)) {
-            if (attempt == 0) {
-              if (lane == 0) bad = 1;
-              break;  // uniform over the wavefront
-            }
-            st |= 2;
-            d = lim > 0.0 && lim <= 1.7e308 ? lim : 1.0;
-          }
-          const double ri = rsqrt_refined(d);
-          rinv[j] = ri;
-          const double lij = D[i * LDB + j] * ri;
-          wave_sync();  // every lane has read the column before it changes
-          if (q == 0 && i > j) D[i * LDB + j] = lij;
-          if (lane == 0) D[j * LDB + j] = d * ri;
-          wave_sync();
+        double a[4];
 #pragma unroll
-          for (int mm = 0; mm < 4; ++mm) {
-            const int c = q + 4 * mm;
-            if (c > j && c <= i) D[i * LDB + c] = fma(-lij, D[c * LDB + j], D[i * LDB + c]);
+        for (int r = 0; r < 4; ++r) a[r] = D[i * LDB + 4 * q + r];
+        double rinv[CB];
+        bool broke = false;
+#pragma unroll
+        for (int j = 0; j < CB; ++j) {
+          const int jq = j >> 2, jr = j & 3;
+          double d = __shfl(a[jr], CB * jq + j);
+          const double lim = 64.0 * u * dref[J * CB + j];
+          // multipliers of column j before scaling: A[i][j] for this row and
+          // A[c][j] for this lane's columns c = 4 q + r
+          const double li_raw = __shfl(a[jr], CB * jq + i);
+          double lc_raw[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) lc_raw[r] = __shfl(a[jr], CB * jq + 4 * q + r);
+          // the pivot test, wavefront-uniform; after a breakdown of the
+          // unshifted attempt the remaining columns are skipped (no early
+          // exit, so that the loop unrolls and a[], rinv[] stay in registers)
+          const bool fail = !__builtin_amdgcn_readfirstlane((int)(d > lim && d <= 1.7e308));
+          if (fail && attempt == 0) broke = true;
+          if (!broke) {
+            if (fail) {
+              st |= 2;
+              d = lim > 0.0 && lim <= 1.7e308 ? lim : 1.0;
+            }
+            const double ri = rsqrt_refined(d);
+            rinv[j] = ri;
+            const double lij = li_raw * ri;
+            if (q == jq && i >= j) a[jr] = i == j ? d * ri : lij;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int c = 4 * q + r;
+              if (c > j && c <= i) a[r] = fma(-lij, lc_raw[r] * ri, a[r]);
+            }
           }
-          wave_sync();
         }
+        if (broke && lane == 0) bad = 1;
+        if (!broke) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (4 * q + r <= i) D[i * LDB + 4 * q + r] = a[r];
+        }
+        wave_sync();  // the factor is in LDS before the inverse reads it
         // inverse of the diagonal block, column r16 by forward substitution
         // with the pivots' reciprocals (lanes 0..15); zeros above its diagonal
-        if (lane < CB) {
+        if (lane < CB && !broke) {
           const int c = lane;
           double x[CB];
 #pragma unroll
@@ -213,7 +234,8 @@ __global__ __launch_bounds__(CT) void cholesky_kernel(const double* __restrict__
   // R = L^T, by 16 x 16 blocks of R: R[row][col] = L[col][row] for row <= col
   if (R) {
     for (int Ib = 0; Ib < nb; ++Ib)
-      for (int Jb = 0; Jb < nb; ++Jb) {
+#pragma unroll
+      for (int Jb = 0; Jb < NBMAX; ++Jb) {
         const int rr = tid >> 4, cc = tid & 15, row = CB * Ib + rr, col = CB * Jb + cc;
         if (row < k && col < k)
           R[(int64_t)row * ldr + col] =
@@ -223,7 +245,11 @@ __global__ __launch_bounds__(CT) void cholesky_kernel(const double* __restrict__
   if (Rinv) {
     // X = L^{-1} by block rows; X_II = Dinv[I]
     for (int I = 1; I < nb; ++I) {
-      for (int J = wv; J < I; J += CT / 64) {
+      // block column J costs I - J products: wavefront w takes J = w and
+      // J = 7 - w, which balances the chains (NBMAX = 9)
+      for (int h = 0; h < 2; ++h) {
+        const int J = h == 0 ? wv : NBMAX - 2 - wv;
+        if (J >= I) continue;
         d4v acc{0, 0, 0, 0};
         for (int K = J; K < I; ++K)
           acc = mma_ab(A + bidx(I, K) * BSZ, K == J ? Dinv + J * BSZ : A + bidx(K, J) * BSZ, 1.0,
@@ -238,8 +264,10 @@ __global__ __launch_bounds__(CT) void cholesky_kernel(const double* __restrict__
       __syncthreads();
     }
     // Rinv = X^T by blocks: Rinv[row][col] = X[col][row] for row <= col
+    // (the block column loop unrolled, so that its LDS reads overlap)
     for (int Ib = 0; Ib < nb; ++Ib)
-      for (int Jb = 0; Jb < nb; ++Jb) {
+#pragma unroll
+      for (int Jb = 0; Jb < NBMAX; ++Jb) {
         const int rr = tid >> 4, cc = tid & 15, row = CB * Ib + rr, col = CB * Jb + cc;
         if (row < k && col < k) {
           double v = 0.0;
