@@ -36,7 +36,9 @@ struct ctm_ctx {
   // X is factored on stream_small (a few CUs), the products Ct Q1 and V Q1
   // run on stream_big (the other CUs); disjoint CU masks keep the
   // latency-bound factorization off the products' CUs.  overlap is false if
-  // the masked streams are unavailable.
+  // the masked streams are unavailable.  The two streams belong to the
+  // process (one pair per device, shared by all contexts); a context's work
+  // on them is joined into `stream` by ev_small and ev_big.
   hipStream_t stream_big = nullptr, stream_small = nullptr;
   hipEvent_t ev_big = nullptr, ev_small = nullptr;
   bool overlap = false;
@@ -124,13 +126,12 @@ struct ctm_ctx {
       (void)hipStreamSynchronize(stream2);
       (void)hipStreamDestroy(stream2);
     }
-    for (hipStream_t* q : {&stream_big, &stream_small})
-      if (*q) {
-        (void)hipStreamSynchronize(*q);
-        (void)hipStreamDestroy(*q);
+    // the last work this context put on the shared masked streams
+    for (hipEvent_t e : {ev_big, ev_small})
+      if (e) {
+        (void)hipEventSynchronize(e);
+        (void)hipEventDestroy(e);
       }
-    if (ev_big) (void)hipEventDestroy(ev_big);
-    if (ev_small) (void)hipEventDestroy(ev_small);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
     if (ev_spec) (void)hipEventDestroy(ev_spec);

@@ -35,7 +35,9 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -582,6 +584,41 @@ bool valid_cfg(const ctm_config* cfg, std::string& why) {
   return true;
 }
 
+// The pair of CU-masked streams of the current device (16 CUs for the basis
+// factorization, the others for the products), created on first use and
+// kept for the life of the process: every context on the device shares
+// them, since the runtime gives each masked stream hardware queue resources
+// of its own and creating a pair per context slowed later contexts down.
+// Work from different contexts on the pair is ordered by each context's own
+// events, so sharing costs at most false dependencies.  False if the device
+// has fewer than 64 CUs or the runtime refuses the masks.
+bool masked_streams(hipStream_t* small_s, hipStream_t* big_s) {
+  static std::mutex mu;
+  static std::map<int, std::pair<hipStream_t, hipStream_t>> pool;
+  int dev = 0, ncu = 0;
+  CTM_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = pool.find(dev);
+  if (it == pool.end()) {
+    std::pair<hipStream_t, hipStream_t> q{nullptr, nullptr};
+    CTM_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    if (ncu >= 64) {
+      std::vector<uint32_t> small((ncu + 31) / 32, 0u), big((ncu + 31) / 32, 0u);
+      for (int i = 0; i < ncu; ++i) (i < 16 ? small : big)[i / 32] |= 1u << (i % 32);
+      if (hipExtStreamCreateWithCUMask(&q.first, (uint32_t)small.size(), small.data()) != hipSuccess ||
+          hipExtStreamCreateWithCUMask(&q.second, (uint32_t)big.size(), big.data()) != hipSuccess) {
+        (void)hipGetLastError();
+        if (q.first) (void)hipStreamDestroy(q.first);
+        q = {nullptr, nullptr};
+      }
+    }
+    it = pool.emplace(dev, q).first;
+  }
+  *small_s = it->second.first;
+  *big_s = it->second.second;
+  return *small_s != nullptr && *big_s != nullptr;
+}
+
 void allocate(ctm_ctx* c) {
   const int64_t D2 = c->D2, chi = c->chi, nmax = c->nmax;
   const int64_t dA = (int64_t)c->d * c->D * c->D * c->D;
@@ -612,22 +649,11 @@ void allocate(ctm_ctx* c) {
     // the products.  Streams made with a CU mask are blocking streams, which
     // the legacy default stream would synchronize with at every launch, so
     // with the null stream (or no masked streams) there is no overlap.
-    int dev = 0, ncu = 0;
-    CTM_HIP(hipGetDevice(&dev));
-    CTM_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    if (c->stream != nullptr && ncu >= 64) {
-      std::vector<uint32_t> small((ncu + 31) / 32, 0u), big((ncu + 31) / 32, 0u);
-      for (int i = 0; i < ncu; ++i) (i < 16 ? small : big)[i / 32] |= 1u << (i % 32);
-      if (hipExtStreamCreateWithCUMask(&c->stream_small, (uint32_t)small.size(), small.data()) ==
-              hipSuccess &&
-          hipExtStreamCreateWithCUMask(&c->stream_big, (uint32_t)big.size(), big.data()) ==
-              hipSuccess) {
-        CTM_HIP(hipEventCreateWithFlags(&c->ev_big, hipEventDisableTiming | hipEventDisableSystemFence));
-        CTM_HIP(hipEventCreateWithFlags(&c->ev_small, hipEventDisableTiming | hipEventDisableSystemFence));
-        c->overlap = true;
-      } else {
-        (void)hipGetLastError();
-      }
+    if (c->stream != nullptr &&
+        masked_streams(&c->stream_small, &c->stream_big)) {
+      CTM_HIP(hipEventCreateWithFlags(&c->ev_big, hipEventDisableTiming | hipEventDisableSystemFence));
+      CTM_HIP(hipEventCreateWithFlags(&c->ev_small, hipEventDisableTiming | hipEventDisableSystemFence));
+      c->overlap = true;
     }
     c->chol_status = (int*)c->alloc(sizeof(int) * 4);
   }
