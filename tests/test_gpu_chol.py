@@ -272,3 +272,38 @@ def test_chol_overlapped_fp32_energy():
     print(f"c3 fp32 overlapped: {steps} steps, |dE| = {abs(e - gold['e_site']):.3e}")
     assert ok
     assert abs(e - gold["e_site"]) < 1e-6
+
+
+def test_chol_contexts_sharing_the_masked_streams():
+    """Two contexts alive at once, each on its own stream, share the device's
+    CU-masked stream pair: steps issued alternately from both agree with the
+    same steps of each context run alone on the default stream."""
+    wa = ci.Workload("t", 2, 3, 20, 601, 602)
+    wb = ci.Workload("t", 2, 2, 16, 603, 604)
+    ref = {}
+    for key, w in (("a", wa), ("b", wb)):
+        c = gpu_context(w)
+        c.step(7)
+        ref[key] = [t.clone() for t in c.get_env() if t is not None]
+        torch.cuda.synchronize()
+        c.close()
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    with torch.cuda.stream(sa):
+        a = gpu_context(wa)
+    with torch.cuda.stream(sb):
+        b = gpu_context(wb)
+    for _ in range(7):
+        with torch.cuda.stream(sa):
+            a.step(1)
+        with torch.cuda.stream(sb):
+            b.step(1)
+    with torch.cuda.stream(sa):
+        got_a = [t.clone() for t in a.get_env() if t is not None]
+    with torch.cuda.stream(sb):
+        got_b = [t.clone() for t in b.get_env() if t is not None]
+    torch.cuda.synchronize()
+    a.close()
+    b.close()
+    for got, key in ((got_a, "a"), (got_b, "b")):
+        for x, y in zip(got, ref[key]):
+            assert (x - y).abs().max().item() < 1e-12
