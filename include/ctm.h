@@ -74,8 +74,9 @@ enum {
  *               a Gram matrix that breaks down even when shifted sets the
  *               non-finite flag (CTM_ENONFINITE).  Needs chi <= 144.
  *               On a stream other than the NULL stream, FP64 and FP32 update
- *               steps form Ct Q1 and V Q1 on two CU-masked streams of the
- *               context (16 CUs factor X, the rest multiply) and finish the
+ *               steps form Ct Q1 and V Q1 on a pair of CU-masked streams
+ *               that the library creates once per device and shares among
+ *               its contexts (16 CUs factor X, the rest multiply) and finish the
  *               renormalization with (Ct Q1) gs(X) and (V Q1) gs(X); on the
  *               NULL stream (which synchronizes with such streams) the steps
  *               run in sequence.  Same result to rounding either way. */
